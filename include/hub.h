@@ -1,0 +1,152 @@
+/*
+ * hub.h - C ABI of the MI355X (gfx950) honeycomb Hubbard-model HMC hot path.
+ *
+ * The library applies the fermion matrix M[phi] of the Hubbard-Stratonovich
+ * transformed Hubbard model on the honeycomb lattice (paper Sec. 2, eq. "ferm_op"
+ * in its exponential transfer-matrix form), solves (M M^dag) x = chi with
+ * conjugate gradients, and computes the pseudofermion force dS/dphi of
+ * S = chi^dag (M M^dag)^{-1} chi (Sec. 2, eq. "hamiltonian").
+ *
+ * Operator (all indices mod Nt, E = exp(delta*kappa*K), delta = beta/Nt):
+ *     (M v)_t     = v_t - B_t     E (e^{i phi_{t-1}} * v_{t-1})
+ *     (M^dag v)_t = v_t - B_{t+1} e^{-i phi_t} * (E v_{t+1})
+ * with B_0 = -1 (antiperiodic wrap) and B_t = +1 otherwise.  K is the
+ * nearest-neighbour hopping matrix of the L x L honeycomb torus (Sec. 1,
+ * fig. "honeycomb_lattice"): A(n) is bonded to B(n), B(n-e1), B(n-e2).
+ *
+ * Layouts (C-contiguous, fastest index last):
+ *     site x = s*L*L + n1*L + n2      (s = 0 for sublattice A, 1 for B)
+ *     V = 2*L*L sites per slice, N = V*Nt entries per vector
+ *     phi    : double [Nt][V]                     (float for the *_c64 calls)
+ *     vectors: complex128 [nrhs][Nt][V], interleaved (re, im) doubles
+ *              (complex64 [nrhs][Nt][V] for the *_c64 calls)
+ *     force  : double [Nt][V]
+ *
+ * Ownership: every array argument is a DEVICE pointer on the context's device,
+ * owned by the caller; the library keeps no pointer after a call returns.  The
+ * context owns its tables and workspace (allocated by hub_create / lazily by
+ * the first hub_cg_solve, freed by hub_destroy).
+ *
+ * Streams: every call enqueues its work on `stream` (a hipStream_t; NULL means
+ * the default stream) and returns without synchronising, except hub_cg_solve,
+ * which synchronises on `stream` to read its convergence status.
+ *
+ * Errors: calls return a hub_status and never abort.  Arguments are validated
+ * before anything is launched; hub_last_error() returns a thread-local message
+ * describing the last non-OK status of the calling thread.
+ *
+ * Threads: a context may be used from one host thread at a time.  Calls on one
+ * context that overlap in time (on different streams) share its workspace and race.
+ */
+#ifndef HUB_H
+#define HUB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hub_ctx hub_ctx;
+
+typedef enum {
+    HUB_OK = 0,
+    HUB_ERR_ARG = 1,        /* invalid argument (null pointer, size, aliasing, option) */
+    HUB_ERR_DEVICE = 2,     /* a HIP runtime call failed                               */
+    HUB_ERR_NOMEM = 3,      /* device allocation failed                                */
+    HUB_ERR_NOCONV = 4,     /* CG reached max_iter before the true residual met tol     */
+    HUB_ERR_NONFINITE = 5   /* NaN or Inf appeared in a CG scalar                      */
+} hub_status;
+
+typedef enum { HUB_PREC_FP64 = 0, HUB_PREC_MIXED = 1 } hub_prec;
+
+/* Which kernel layout applies E: AUTO picks the fused one-slice-per-workgroup
+ * kernel when a slice fits in LDS, else the three-kernel split path.  FUSED and
+ * SPLIT force one (FUSED fails with HUB_ERR_ARG when the slice does not fit). */
+typedef enum { HUB_PATH_AUTO = 0, HUB_PATH_FUSED = 1, HUB_PATH_SPLIT = 2 } hub_path;
+
+typedef struct {
+    int32_t L;          /* torus extent, 1 <= L <= 1024; every prime factor of L must be <= 17 */
+    int32_t Nt;         /* time slices, Nt >= 1                                                 */
+    double beta;        /* inverse temperature, delta = beta/Nt                                 */
+    double kappa;       /* hopping amplitude                                                    */
+    int32_t nrhs_max;   /* largest nrhs any call on this context will pass, >= 1                */
+    int32_t path;       /* hub_path                                                              */
+} hub_params;
+
+typedef struct {
+    double tol;             /* stop when ||chi - M M^dag x|| <= tol ||chi|| (true FP64 residual) */
+    int32_t max_iter;       /* iteration cap per right-hand side, >= 1                          */
+    int32_t reliable_every; /* FP64 residual recomputation every this many iterations, >= 1     */
+    int32_t prec;           /* hub_prec: FP64 throughout, or FP32 inner iterations               */
+    int32_t use_x0;         /* 1: x holds the initial guess on entry; 0: start from x = 0       */
+} hub_cg_opts;
+
+typedef struct {
+    int32_t iters;              /* CG iterations performed for this right-hand side           */
+    int32_t reliable_updates;   /* FP64 residual recomputations                               */
+    double true_rel_res;        /* ||chi - A x|| / ||chi|| in FP64 at exit                    */
+    double recursive_rel_res;   /* the iterated residual's ||r|| / ||chi|| at exit            */
+} hub_cg_info;
+
+/* Create a context on the current HIP device: builds the momentum-space hopping
+ * table E(k) (Sec. 1: bands +-kappa|f(k)|) and the DFT roots of unity in FP64.
+ * `stream` is used for the table uploads.  *out is set to NULL on failure. */
+hub_status hub_create(const hub_params* params, void* stream, hub_ctx** out);
+
+/* Release every device allocation of the context (synchronises the device).  NULL is a no-op. */
+void hub_destroy(hub_ctx* ctx);
+
+/* out = M[phi] in  (Sec. 2, eq. "ferm_op", exponential form), FP64.
+ * in and out: complex128 [nrhs][Nt][V]; must not overlap.  1 <= nrhs <= nrhs_max. */
+hub_status hub_apply_M(hub_ctx* ctx, const double* phi, const void* in, void* out,
+                       int32_t nrhs, void* stream);
+
+/* out = M[phi]^dag in, FP64.  Same layout and rules as hub_apply_M. */
+hub_status hub_apply_Mdag(hub_ctx* ctx, const double* phi, const void* in, void* out,
+                          int32_t nrhs, void* stream);
+
+/* FP32 variants of the two operators (complex64 vectors, float phi): the kernels
+ * that the mixed-precision CG iterates with. */
+hub_status hub_apply_M_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,
+                           int32_t nrhs, void* stream);
+hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,
+                              int32_t nrhs, void* stream);
+
+/* Solve (M M^dag) x = chi for nrhs independent right-hand sides (Sec. 2, eq.
+ * "hamiltonian": the pseudofermion term needs (M M^dag)^{-1} chi).  Conjugate
+ * gradients from x0 = 0 (or x on entry when opts->use_x0), all reductions in FP64.
+ * With opts->prec == HUB_PREC_MIXED the iterations run in FP32 and every
+ * reliable_every iterations (or as soon as the iterated residual meets tol) the
+ * FP64 solution is updated and the FP64 residual recomputed.  Convergence is
+ * always judged on the true FP64 residual.
+ * chi, x: complex128 [nrhs][Nt][V], must not overlap.  info_host: nrhs entries
+ * in HOST memory (may be NULL).  Returns HUB_ERR_NOCONV (x = last FP64 iterate,
+ * info filled) or HUB_ERR_NONFINITE when the iteration breaks down. */
+hub_status hub_cg_solve(hub_ctx* ctx, const double* phi, const void* chi, void* x, int32_t nrhs,
+                        const hub_cg_opts* opts, hub_cg_info* info_host, void* stream);
+
+/* dS/dphi of the pseudofermion action S = sum_r chi_r^dag x_r, x_r = (M M^dag)^{-1} chi_r,
+ * from the solutions x (complex128 [nrhs][Nt][V]):
+ *     dSdphi[t][z] = sum_r -2 B_{t+1} Im( e^{i phi_{t,z}} x_{r,t,z} conj((E x_{r,t+1})_z) ).
+ * dSdphi (double [Nt][V]) is overwritten.  The Gaussian term phi/(delta U) is the caller's. */
+hub_status hub_force(hub_ctx* ctx, const double* phi, const void* x, double* dSdphi,
+                     int32_t nrhs, void* stream);
+
+/* S_dev[0] = sum_r Re(chi_r^dag x_r) in FP64 (the pseudofermion action of eq.
+ * "hamiltonian" when x solves M M^dag x = chi).  S_dev: one double on the device. */
+hub_status hub_action(hub_ctx* ctx, const void* chi, const void* x, int32_t nrhs,
+                      double* S_dev, void* stream);
+
+/* Report the kernel path the context uses (hub_path value, never AUTO) and the
+ * LDS bytes per workgroup of its operator kernel. */
+hub_status hub_query(const hub_ctx* ctx, int32_t* path, int32_t* lds_bytes);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* hub_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HUB_H */

@@ -1,0 +1,174 @@
+"""MI355X (gfx950) hot path of honeycomb Hubbard-model Hybrid Monte Carlo.
+
+A thin Python binding over the C ABI of libhubhip.so (include/hub.h): torch
+tensors supply device memory and the current HIP stream; every arithmetic step
+runs in the library's HIP kernels.  Names follow the paper (Sec. 2): the
+fermion matrix M[phi], the pseudofermion chi, the solution x = (M M^dag)^{-1} chi,
+the action S = chi^dag x and its force dS/dphi.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import HubError, HUB_ERR_NOCONV, HUB_OK
+
+__all__ = ["Hubbard", "CgResult", "HubError", "PseudofermionAction"]
+
+_PREC = {"fp64": _lib.HUB_PREC_FP64, "mixed": _lib.HUB_PREC_MIXED}
+_PATH = {"auto": _lib.HUB_PATH_AUTO, "fused": _lib.HUB_PATH_FUSED, "split": _lib.HUB_PATH_SPLIT}
+_PATH_NAME = {v: k for k, v in _PATH.items()}
+
+
+def _stream_ptr(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class CgResult:
+    x: torch.Tensor
+    status: int
+    iters: list
+    reliable_updates: list
+    true_rel_res: list
+    recursive_rel_res: list
+
+    @property
+    def converged(self) -> bool:
+        return self.status == HUB_OK
+
+
+class Hubbard:
+    """One lattice: L x L honeycomb torus (V = 2 L^2 sites), Nt slices, beta, kappa."""
+
+    def __init__(self, L: int, Nt: int, beta: float, kappa: float = 1.0, nrhs_max: int = 1,
+                 path: str = "auto", device=None):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.L, self.Nt, self.beta, self.kappa, self.nrhs_max = L, Nt, float(beta), float(kappa), nrhs_max
+        self.V = 2 * L * L
+        self.N = self.V * Nt
+        prm = _lib.HubParams(L, Nt, float(beta), float(kappa), nrhs_max, _PATH[path])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_create(ctypes.byref(prm), _stream_ptr(self.device), ctypes.byref(h)))
+        self._h = h
+        p, lds = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(self.lib.hub_query(self._h, ctypes.byref(p), ctypes.byref(lds)))
+        self.path = _PATH_NAME[p.value]
+        self.lds_bytes = lds.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.hub_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ argument checks
+    def _vec(self, v: torch.Tensor, dtype=torch.complex128, name="vector") -> tuple[torch.Tensor, int]:
+        if not isinstance(v, torch.Tensor) or v.device != self.device:
+            raise ValueError(f"{name} must be a tensor on {self.device}")
+        if v.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {v.dtype}")
+        if v.dim() == 2:
+            v = v.unsqueeze(0)
+        if v.dim() != 3 or tuple(v.shape[1:]) != (self.Nt, self.V):
+            raise ValueError(f"{name} must have shape [nrhs, {self.Nt}, {self.V}], got {tuple(v.shape)}")
+        if not v.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return v, v.shape[0]
+
+    def _phi(self, phi: torch.Tensor, dtype=torch.float64) -> torch.Tensor:
+        if not isinstance(phi, torch.Tensor) or phi.device != self.device or phi.dtype != dtype:
+            raise ValueError(f"phi must be a {dtype} tensor on {self.device}")
+        if tuple(phi.shape) != (self.Nt, self.V) or not phi.is_contiguous():
+            raise ValueError(f"phi must be contiguous with shape [{self.Nt}, {self.V}]")
+        return phi
+
+    @staticmethod
+    def _p(t: torch.Tensor) -> ctypes.c_void_p:
+        return ctypes.c_void_p(t.data_ptr())
+
+    # ------------------------------------------------------------------ operators
+    def _apply(self, fn, phi, v, cdtype, rdtype, out=None):
+        phi = self._phi(phi, rdtype)
+        v3, nrhs = self._vec(v, cdtype)
+        o = torch.empty_like(v3) if out is None else out
+        with torch.cuda.device(self.device):
+            _lib.check(fn(self._h, self._p(phi), self._p(v3), self._p(o), nrhs, _stream_ptr(self.device)))
+        return o if v.dim() == 3 else o[0]
+
+    def apply_M(self, phi, v, out=None):
+        """M[phi] v in FP64 (complex128 [nrhs, Nt, V] or [Nt, V])."""
+        return self._apply(self.lib.hub_apply_M, phi, v, torch.complex128, torch.float64, out)
+
+    def apply_Mdag(self, phi, v, out=None):
+        """M[phi]^dag v in FP64."""
+        return self._apply(self.lib.hub_apply_Mdag, phi, v, torch.complex128, torch.float64, out)
+
+    def apply_M_c64(self, phi32, v, out=None):
+        """M[phi] v in FP32 (complex64 vectors, float32 phi)."""
+        return self._apply(self.lib.hub_apply_M_c64, phi32, v, torch.complex64, torch.float32, out)
+
+    def apply_Mdag_c64(self, phi32, v, out=None):
+        """M[phi]^dag v in FP32."""
+        return self._apply(self.lib.hub_apply_Mdag_c64, phi32, v, torch.complex64, torch.float32, out)
+
+    # ------------------------------------------------------------------ solver, action, force
+    def cg_solve(self, phi, chi, tol: float = 1e-10, max_iter: int = 100000, prec: str = "fp64",
+                 reliable_every: int = 50, x0=None, raise_on_error: bool = True) -> CgResult:
+        """x = (M M^dag)^{-1} chi by conjugate gradients (true FP64 residual <= tol)."""
+        phi = self._phi(phi)
+        chi3, nrhs = self._vec(chi, name="chi")
+        if x0 is None:
+            x = torch.empty_like(chi3)
+            use_x0 = 0
+        else:
+            x, _ = self._vec(x0.clone(), name="x0")
+            use_x0 = 1
+        opts = _lib.HubCgOpts(float(tol), int(max_iter), int(reliable_every), _PREC[prec], use_x0)
+        info = (_lib.HubCgInfo * nrhs)()
+        with torch.cuda.device(self.device):
+            st = self.lib.hub_cg_solve(self._h, self._p(phi), self._p(chi3), self._p(x), nrhs,
+                                       ctypes.byref(opts), info, _stream_ptr(self.device))
+        if st not in (HUB_OK, HUB_ERR_NOCONV) and raise_on_error:
+            _lib.check(st)
+        if st == HUB_ERR_NOCONV and raise_on_error:
+            _lib.check(st)
+        res = CgResult(x if chi.dim() == 3 else x[0], st,
+                       [i.iters for i in info], [i.reliable_updates for i in info],
+                       [i.true_rel_res for i in info], [i.recursive_rel_res for i in info])
+        return res
+
+    def force(self, phi, x, out=None):
+        """dS/dphi (float64 [Nt, V]) of S = chi^dag (M M^dag)^{-1} chi from the solutions x."""
+        phi = self._phi(phi)
+        x3, nrhs = self._vec(x, name="x")
+        g = torch.empty((self.Nt, self.V), dtype=torch.float64, device=self.device) if out is None else out
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_force(self._h, self._p(phi), self._p(x3), self._p(g), nrhs,
+                                          _stream_ptr(self.device)))
+        return g
+
+    def action(self, chi, x):
+        """S = sum_r Re(chi_r^dag x_r) in FP64, as a 0-dim device tensor."""
+        chi3, nrhs = self._vec(chi, name="chi")
+        x3, n2 = self._vec(x, name="x")
+        if n2 != nrhs:
+            raise ValueError("chi and x have different nrhs")
+        S = torch.empty((), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_action(self._h, self._p(chi3), self._p(x3), nrhs, self._p(S),
+                                           _stream_ptr(self.device)))
+        return S
+
+
+from .autograd import PseudofermionAction  # noqa: E402

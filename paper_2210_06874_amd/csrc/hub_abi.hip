@@ -1,0 +1,418 @@
+// C ABI of the hot path: argument validation, context and workspace management,
+// kernel launches and the host side of the conjugate-gradient driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "hub_kernels.hpp"
+
+using namespace hub;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+hub_status fail(hub_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIP_OR_FAIL(expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? HUB_ERR_NOMEM : HUB_ERR_DEVICE,        \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));                    \
+    } while (0)
+
+hub_status launch_check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(HUB_ERR_DEVICE, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return HUB_OK;
+}
+
+SplitGeom split_geom(int L) {
+    SplitGeom g{};
+    int rb0 = std::max(1, std::min(L, 2048 / L));
+    g.nrb = (L + rb0 - 1) / rb0;
+    g.rb = (L + g.nrb - 1) / g.nrb;
+    int cb0 = std::max(1, std::min(L, 1024 / L));
+    g.ncb = (L + cb0 - 1) / cb0;
+    g.cb = (L + g.ncb - 1) / g.ncb;
+    return g;
+}
+
+template <typename R>
+size_t fused_lds(const hub_ctx* c) { return (size_t)(c->V + c->L) * sizeof(cx<R>); }
+
+template <typename R>
+OpTab<R> op_tab(const hub_ctx* c);
+template <>
+OpTab<double> op_tab<double>(const hub_ctx* c) {
+    return {reinterpret_cast<const cx<double>*>(c->roots64), c->etab64, c->plan, c->L, c->V, c->Nt, c->N};
+}
+template <>
+OpTab<float> op_tab<float>(const hub_ctx* c) {
+    return {reinterpret_cast<const cx<float>*>(c->roots32), c->etab32, c->plan, c->L, c->V, c->Nt, c->N};
+}
+
+template <typename K>
+void allow_lds(K kern, size_t bytes) {
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Apply E between a source functor and an epilogue functor over nrhs right-hand sides.
+template <typename R, class Src, class Epi, class Fin>
+hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Fin& fin, int cid,
+                  hipStream_t st, const CgScalars* sc, int gate) {
+    const OpTab<R> T = op_tab<R>(c);
+    RedArgs ra{c->partials, c->counters + cid, c->Nt, nrhs};
+    if (c->path == HUB_PATH_FUSED) {
+        const size_t lds = fused_lds<R>(c);
+        auto kern = k_fused<R, Src, Epi, Fin>;
+        allow_lds(kern, lds);
+        hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads), lds, st, T, src, epi, fin, ra, sc, gate);
+        return launch_check("k_fused");
+    }
+    const SplitGeom G = split_geom(c->L);
+    cx<R>* W = reinterpret_cast<cx<R>*>(c->split_w);
+    const size_t lds_rows = (size_t)(G.rb * c->L + c->L) * sizeof(cx<R>);
+    const size_t lds_cols = (size_t)(2 * c->L * G.cb + c->L) * sizeof(cx<R>);
+    auto k1 = k_split_rows_fwd<R, Src>;
+    auto k2 = k_split_cols<R>;
+    auto k3 = k_split_rows_inv<R, Epi, Fin>;
+    allow_lds(k1, lds_rows);
+    allow_lds(k2, lds_cols);
+    allow_lds(k3, lds_rows);
+    const int nrow_blocks = nrhs * c->Nt * 2 * G.nrb;
+    hipLaunchKernelGGL(k1, dim3(nrow_blocks), dim3(kThreads), lds_rows, st, T, G, src, W, sc, gate);
+    hub_status s = launch_check("k_split_rows_fwd");
+    if (s != HUB_OK) return s;
+    hipLaunchKernelGGL(k2, dim3(nrhs * c->Nt * G.ncb), dim3(kThreads), lds_cols, st, T, G, W, sc, gate);
+    s = launch_check("k_split_cols");
+    if (s != HUB_OK) return s;
+    ra.slots = c->Nt * 2 * G.nrb;
+    hipLaunchKernelGGL(k3, dim3(nrow_blocks), dim3(kThreads), lds_rows, st, T, G,
+                       static_cast<const cx<R>*>(W), epi, fin, ra, sc, gate);
+    return launch_check("k_split_rows_inv");
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+hub_status check_vec_args(const hub_ctx* c, const void* phi, const void* in, const void* out, int nrhs,
+                          size_t elem) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (!phi || !in || !out) return fail(HUB_ERR_ARG, "NULL array argument");
+    if (nrhs < 1 || nrhs > c->nrhs_max)
+        return fail(HUB_ERR_ARG, "nrhs=%d outside [1, nrhs_max=%d]", nrhs, c->nrhs_max);
+    if (overlaps(in, out, (size_t)nrhs * c->N * elem)) return fail(HUB_ERR_ARG, "in and out overlap");
+    return HUB_OK;
+}
+
+template <typename R>
+hub_status apply_M_impl(hub_ctx* c, const R* phi, const void* in, void* out, int nrhs, void* stream) {
+    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>));
+    if (s != HUB_OK) return s;
+    const cx<R>* v = static_cast<const cx<R>*>(in);
+    return run_op<R>(c, nrhs, SrcPhasePrev<R>{v, phi}, EpiM<R>{v, static_cast<cx<R>*>(out)}, FinNone{}, 0,
+                     static_cast<hipStream_t>(stream), nullptr, GATE_NONE);
+}
+
+template <typename R>
+hub_status apply_Mdag_impl(hub_ctx* c, const R* phi, const void* in, void* out, int nrhs, void* stream) {
+    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>));
+    if (s != HUB_OK) return s;
+    const cx<R>* v = static_cast<const cx<R>*>(in);
+    return run_op<R>(c, nrhs, SrcNext<R>{v}, EpiMdag<R>{v, static_cast<cx<R>*>(out), phi}, FinNone{}, 0,
+                     static_cast<hipStream_t>(stream), nullptr, GATE_NONE);
+}
+
+hub_status ensure_cg_workspace(hub_ctx* c) {
+    if (c->cg_ready) return HUB_OK;
+    const size_t vbytes = (size_t)c->nrhs_max * c->N * sizeof(cx<double>);
+    HIP_OR_FAIL(hipMalloc(&c->cg_rhi, vbytes));
+    HIP_OR_FAIL(hipMalloc(&c->cg_tmp, vbytes));
+    HIP_OR_FAIL(hipMalloc(&c->cg_x, vbytes));
+    HIP_OR_FAIL(hipMalloc(&c->cg_r, vbytes));
+    HIP_OR_FAIL(hipMalloc(&c->cg_p, vbytes));
+    HIP_OR_FAIL(hipMalloc(&c->cg_t, vbytes));
+    HIP_OR_FAIL(hipMalloc(&c->phi32, (size_t)c->N * sizeof(float)));
+    HIP_OR_FAIL(hipMalloc(&c->scal, (size_t)c->nrhs_max * sizeof(CgScalars)));
+    HIP_OR_FAIL(hipHostMalloc(&c->scal_host, (size_t)c->nrhs_max * sizeof(CgScalars), hipHostMallocDefault));
+    c->cg_ready = true;
+    return HUB_OK;
+}
+
+// The solver proper, templated on the precision of the inner iterations.
+template <typename Rlo>
+hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<double>* xhi, int nrhs,
+                   const hub_cg_opts& o, hub_cg_info* info, hipStream_t st) {
+    const Rlo* phi_lo;
+    if constexpr (sizeof(Rlo) == sizeof(float)) {
+        hipLaunchKernelGGL(k_to_float, dim3(1024), dim3(kThreads), 0, st, phi, c->phi32, c->N);
+        hub_status s = launch_check("k_to_float");
+        if (s != HUB_OK) return s;
+        phi_lo = reinterpret_cast<const Rlo*>(c->phi32);
+    } else {
+        phi_lo = reinterpret_cast<const Rlo*>(phi);
+    }
+    cx<double>* rhi = static_cast<cx<double>*>(c->cg_rhi);
+    cx<double>* tmp = static_cast<cx<double>*>(c->cg_tmp);
+    cx<Rlo>* xlo = static_cast<cx<Rlo>*>(c->cg_x);
+    cx<Rlo>* rlo = static_cast<cx<Rlo>*>(c->cg_r);
+    cx<Rlo>* p = static_cast<cx<Rlo>*>(c->cg_p);
+    cx<Rlo>* tv = static_cast<cx<Rlo>*>(c->cg_t);
+    CgScalars* sc = c->scal;
+    const int zero_start = o.use_x0 ? 0 : 1;
+    const int blocks = nrhs * c->Nt;
+
+    RedArgs ra{c->partials, c->counters + 1, c->Nt, nrhs};
+    hipLaunchKernelGGL(k_cg_init<Rlo>, dim3(blocks), dim3(kThreads), 0, st, chi, xhi, rhi, xlo, rlo, p, c->V,
+                       c->Nt, zero_start, FinInit{sc, o.tol, zero_start}, ra);
+    hub_status s = launch_check("k_cg_init");
+    if (s != HUB_OK) return s;
+
+    auto reliable_update = [&]() -> hub_status {
+        hipLaunchKernelGGL(k_fold_solution<Rlo>, dim3(blocks), dim3(kThreads), 0, st, xhi, xlo, c->V, c->Nt,
+                           static_cast<const CgScalars*>(sc));
+        hub_status r = launch_check("k_fold_solution");
+        if (r != HUB_OK) return r;
+        r = run_op<double>(c, nrhs, SrcNext<double>{xhi}, EpiMdag<double>{xhi, tmp, phi}, FinNone{}, 2, st, sc,
+                           GATE_NOTDONE);
+        if (r != HUB_OK) return r;
+        return run_op<double>(c, nrhs, SrcPhasePrev<double>{tmp, phi},
+                              EpiResidual<Rlo>{tmp, chi, rhi, rlo}, FinResidual{sc}, 3, st, sc, GATE_NOTDONE);
+    };
+
+    if (!zero_start) {
+        hipLaunchKernelGGL(k_zero_trivial, dim3(blocks), dim3(kThreads), 0, st, xhi, c->V, c->Nt,
+                           static_cast<const CgScalars*>(sc));
+        s = launch_check("k_zero_trivial");
+        if (s != HUB_OK) return s;
+        s = reliable_update();
+        if (s != HUB_OK) return s;
+    }
+
+    hub_status result = HUB_OK;
+    long long it = 0;
+    const int every = o.reliable_every;
+    for (;;) {
+        HIP_OR_FAIL(hipMemcpyAsync(c->scal_host, sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(hipStreamSynchronize(st));
+        bool all_done = true, bad = false;
+        for (int r = 0; r < nrhs; ++r) {
+            all_done &= c->scal_host[r].done != 0;
+            bad |= c->scal_host[r].nonfinite != 0;
+        }
+        if (bad) {
+            result = fail(HUB_ERR_NONFINITE, "CG breakdown: non-finite or non-positive scalar");
+            break;
+        }
+        if (all_done) break;
+        if (it >= o.max_iter) {
+            result = fail(HUB_ERR_NOCONV, "CG did not reach tol=%g within max_iter=%d", o.tol, o.max_iter);
+            break;
+        }
+        const long long n = std::min<long long>(every, o.max_iter - it);
+        for (long long k = 0; k < n; ++k) {
+            s = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p, sc}, EpiSearchMdag<Rlo>{rlo, p, tv, phi_lo, sc},
+                            FinSearch{sc}, 4, st, sc, GATE_ACTIVE);
+            if (s != HUB_OK) return s;
+            s = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo>{tv, phi_lo}, EpiUpdate<Rlo>{tv, p, xlo, rlo, sc},
+                            FinUpdate{sc}, 5, st, sc, GATE_ACTIVE);
+            if (s != HUB_OK) return s;
+        }
+        it += n;
+        s = reliable_update();
+        if (s != HUB_OK) return s;
+    }
+    if (info) {
+        for (int r = 0; r < nrhs; ++r) {
+            const CgScalars& h = c->scal_host[r];
+            const double cc = h.chichi > 0 ? h.chichi : 1.0;
+            info[r].iters = h.iters;
+            info[r].reliable_updates = h.reliable;
+            info[r].true_rel_res = std::sqrt(h.true_rr / cc);
+            info[r].recursive_rel_res = std::sqrt(h.rec_rr / cc);
+        }
+    }
+    return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hub_last_error(void) { return g_err; }
+
+hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
+    if (!out) return fail(HUB_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!prm) return fail(HUB_ERR_ARG, "params is NULL");
+    if (prm->L < 1 || prm->L > 1024) return fail(HUB_ERR_ARG, "L=%d outside [1, 1024]", prm->L);
+    if (prm->Nt < 1) return fail(HUB_ERR_ARG, "Nt=%d < 1", prm->Nt);
+    if (prm->nrhs_max < 1) return fail(HUB_ERR_ARG, "nrhs_max=%d < 1", prm->nrhs_max);
+    if (!std::isfinite(prm->beta) || !std::isfinite(prm->kappa))
+        return fail(HUB_ERR_ARG, "beta and kappa must be finite");
+    if (prm->path < HUB_PATH_AUTO || prm->path > HUB_PATH_SPLIT) return fail(HUB_ERR_ARG, "bad path %d", prm->path);
+    FftPlan plan{};
+    if (!make_plan(prm->L, &plan))
+        return fail(HUB_ERR_ARG, "L=%d has a prime factor above 17", prm->L);
+    const long long N = 2LL * prm->L * prm->L * prm->Nt;
+    if ((long long)prm->nrhs_max * N >= (1LL << 40)) return fail(HUB_ERR_ARG, "problem too large");
+
+    hub_ctx* c = new hub_ctx();
+    c->L = prm->L;
+    c->Nt = prm->Nt;
+    c->V = 2 * prm->L * prm->L;
+    c->N = N;
+    c->nrhs_max = prm->nrhs_max;
+    c->beta = prm->beta;
+    c->kappa = prm->kappa;
+    c->delta = prm->beta / prm->Nt;
+    c->plan = plan;
+    auto bail = [&](hub_status s) {
+        hub_destroy(c);
+        return s;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(HUB_ERR_DEVICE, "no HIP device"));
+    if (hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+        return bail(fail(HUB_ERR_DEVICE, "cannot query LDS size"));
+    c->lds_fused64 = (int)fused_lds<double>(c);
+    c->lds_fused32 = (int)fused_lds<float>(c);
+    const int reserve = 1024;   // static LDS of the reduction
+    const bool fits = c->lds_fused64 + reserve <= c->max_lds;
+    if (prm->path == HUB_PATH_FUSED && !fits)
+        return bail(fail(HUB_ERR_ARG, "fused path needs %d B of LDS, device has %d", c->lds_fused64, c->max_lds));
+    c->path = (prm->path == HUB_PATH_SPLIT || (prm->path == HUB_PATH_AUTO && !fits)) ? HUB_PATH_SPLIT
+                                                                                      : HUB_PATH_FUSED;
+
+    std::vector<double> roots, etab;
+    build_tables(plan, c->delta * c->kappa, roots, etab);
+    std::vector<float> roots32(roots.begin(), roots.end()), etab32(etab.begin(), etab.end());
+    hipStream_t st = static_cast<hipStream_t>(stream);
+#define CREATE_OR_BAIL(expr)                                                                   \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return bail(fail(e_ == hipErrorOutOfMemory ? HUB_ERR_NOMEM : HUB_ERR_DEVICE,       \
+                             "%s failed: %s", #expr, hipGetErrorString(e_)));                  \
+    } while (0)
+    CREATE_OR_BAIL(hipMalloc(&c->roots64, roots.size() * sizeof(double)));
+    CREATE_OR_BAIL(hipMalloc(&c->roots32, roots.size() * sizeof(float)));
+    CREATE_OR_BAIL(hipMalloc(&c->etab64, etab.size() * sizeof(double)));
+    CREATE_OR_BAIL(hipMalloc(&c->etab32, etab.size() * sizeof(float)));
+    CREATE_OR_BAIL(hipMemcpyAsync(c->roots64, roots.data(), roots.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    CREATE_OR_BAIL(hipMemcpyAsync(c->roots32, roots32.data(), roots32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    CREATE_OR_BAIL(hipMemcpyAsync(c->etab64, etab.data(), etab.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    CREATE_OR_BAIL(hipMemcpyAsync(c->etab32, etab32.data(), etab32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+
+    const SplitGeom G = split_geom(c->L);
+    c->max_partials = std::max(c->Nt, c->Nt * 2 * G.nrb);
+    CREATE_OR_BAIL(hipMalloc(&c->partials, (size_t)c->nrhs_max * c->max_partials * sizeof(double)));
+    CREATE_OR_BAIL(hipMalloc(&c->counters, kNumCounters * sizeof(unsigned int)));
+    CREATE_OR_BAIL(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(unsigned int), st));
+    CREATE_OR_BAIL(hipMalloc(&c->red_out, 8 * sizeof(double)));
+    if (c->path == HUB_PATH_SPLIT)
+        CREATE_OR_BAIL(hipMalloc(&c->split_w, (size_t)c->nrhs_max * c->N * sizeof(cx<double>)));
+    CREATE_OR_BAIL(hipStreamSynchronize(st));   // host vectors above go out of scope
+#undef CREATE_OR_BAIL
+    *out = c;
+    return HUB_OK;
+}
+
+void hub_destroy(hub_ctx* c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    void* dev[] = {c->roots64, c->roots32, c->etab64, c->etab32, c->partials, c->counters, c->red_out,
+                   c->split_w, c->cg_xhi, c->cg_rhi, c->cg_tmp, c->cg_x, c->cg_r, c->cg_p, c->cg_t,
+                   c->phi32, c->scal, c->force_tmp};
+    for (void* p : dev)
+        if (p) (void)hipFree(p);
+    if (c->scal_host) (void)hipHostFree(c->scal_host);
+    delete c;
+}
+
+hub_status hub_apply_M(hub_ctx* c, const double* phi, const void* in, void* out, int32_t nrhs, void* st) {
+    return apply_M_impl<double>(c, phi, in, out, nrhs, st);
+}
+hub_status hub_apply_Mdag(hub_ctx* c, const double* phi, const void* in, void* out, int32_t nrhs, void* st) {
+    return apply_Mdag_impl<double>(c, phi, in, out, nrhs, st);
+}
+hub_status hub_apply_M_c64(hub_ctx* c, const float* phi, const void* in, void* out, int32_t nrhs, void* st) {
+    return apply_M_impl<float>(c, phi, in, out, nrhs, st);
+}
+hub_status hub_apply_Mdag_c64(hub_ctx* c, const float* phi, const void* in, void* out, int32_t nrhs, void* st) {
+    return apply_Mdag_impl<float>(c, phi, in, out, nrhs, st);
+}
+
+hub_status hub_cg_solve(hub_ctx* c, const double* phi, const void* chi, void* x, int32_t nrhs,
+                        const hub_cg_opts* opts, hub_cg_info* info, void* stream) {
+    hub_status s = check_vec_args(c, phi, chi, x, nrhs, sizeof(cx<double>));
+    if (s != HUB_OK) return s;
+    if (!opts) return fail(HUB_ERR_ARG, "opts is NULL");
+    if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) return fail(HUB_ERR_ARG, "tol must be > 0");
+    if (opts->max_iter < 1) return fail(HUB_ERR_ARG, "max_iter must be >= 1");
+    if (opts->reliable_every < 1) return fail(HUB_ERR_ARG, "reliable_every must be >= 1");
+    if (opts->prec != HUB_PREC_FP64 && opts->prec != HUB_PREC_MIXED) return fail(HUB_ERR_ARG, "bad prec");
+    if (opts->use_x0 != 0 && opts->use_x0 != 1) return fail(HUB_ERR_ARG, "use_x0 must be 0 or 1");
+    s = ensure_cg_workspace(c);
+    if (s != HUB_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const cx<double>* chi_c = static_cast<const cx<double>*>(chi);
+    cx<double>* x_c = static_cast<cx<double>*>(x);
+    if (opts->prec == HUB_PREC_MIXED) return cg_impl<float>(c, phi, chi_c, x_c, nrhs, *opts, info, st);
+    return cg_impl<double>(c, phi, chi_c, x_c, nrhs, *opts, info, st);
+}
+
+hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, int32_t nrhs, void* stream) {
+    hub_status s = check_vec_args(c, phi, x, g, nrhs, sizeof(cx<double>));
+    if (s != HUB_OK) return s;
+    if (overlaps(g, phi, (size_t)c->N * sizeof(double))) return fail(HUB_ERR_ARG, "dSdphi overlaps phi");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const cx<double>* xv = static_cast<const cx<double>*>(x);
+    if (nrhs == 1)
+        return run_op<double>(c, 1, SrcNext<double>{xv}, EpiForce{xv, phi, g, 0}, FinNone{}, 0, st, nullptr,
+                              GATE_NONE);
+    if (!c->force_tmp) HIP_OR_FAIL(hipMalloc(&c->force_tmp, (size_t)c->nrhs_max * c->N * sizeof(double)));
+    s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, phi, c->force_tmp, c->N}, FinNone{}, 0, st,
+                       nullptr, GATE_NONE);
+    if (s != HUB_OK) return s;
+    hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, c->force_tmp, g, c->N, nrhs);
+    return launch_check("k_sum_rhs");
+}
+
+hub_status hub_action(hub_ctx* c, const void* chi, const void* x, int32_t nrhs, double* S_dev, void* stream) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (!chi || !x || !S_dev) return fail(HUB_ERR_ARG, "NULL array argument");
+    if (nrhs < 1 || nrhs > c->nrhs_max) return fail(HUB_ERR_ARG, "nrhs=%d outside [1, %d]", nrhs, c->nrhs_max);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    RedArgs ra{c->partials, c->counters + 6, c->Nt, nrhs};
+    hipLaunchKernelGGL(k_dot_re, dim3(nrhs * c->Nt), dim3(kThreads), 0, st, static_cast<const cx<double>*>(chi),
+                       static_cast<const cx<double>*>(x), c->V, c->Nt, FinStore{S_dev, nrhs}, ra);
+    return launch_check("k_dot_re");
+}
+
+hub_status hub_query(const hub_ctx* c, int32_t* path, int32_t* lds_bytes) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (path) *path = c->path;
+    if (lds_bytes) {
+        const SplitGeom G = split_geom(c->L);
+        *lds_bytes = c->path == HUB_PATH_FUSED ? c->lds_fused64
+                                               : (int)((2 * c->L * G.cb + c->L) * sizeof(cx<double>));
+    }
+    return HUB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal declarations shared by the host ABI, the tables and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hub.h"
+
+namespace hub {
+
+constexpr int kMaxStages = 12;     // L <= 1024 has at most 10 prime factors
+constexpr int kNumCounters = 8;    // last-block counters, one per kernel role
+
+// Mixed-radix factorisation of L used by every in-LDS transform.  Stage q works
+// on blocks of length len[q] = L / (radix[0] * ... * radix[q-1]).
+struct FftPlan {
+    int L;
+    int nst;
+    int radix[kMaxStages];
+    int len[kMaxStages];
+};
+
+bool make_plan(int L, FftPlan* plan);
+
+// Position of momentum index k (0 <= k < L) after the in-place forward transform:
+// the transform leaves frequencies in mixed-radix digit-reversed order.
+int digit_reversed_position(const FftPlan& plan, int k);
+
+// Host-side FP64 tables.
+//   roots[m]   = e^{-2 pi i m / L}, m = 0..L-1, angles from the integer m (exact), as (re, im)
+//   etab[p]    = (c, Re sf, Im sf, 0) / L^2 at transform position p = p1*L + p2, where
+//                k = (k1, k2) is the momentum stored at p, f = 1 + e^{-i k1} + e^{-i k2},
+//                c = cosh(dk |f|), s = sinh(dk |f|)/|f| (-> dk at |f| = 0), sf = s*f.
+void build_tables(const FftPlan& plan, double delta_kappa, std::vector<double>& roots,
+                  std::vector<double>& etab);
+
+// Per-right-hand-side CG scalars kept on the device (all FP64).
+struct CgScalars {
+    double rr;        // ||r||^2 of the iterated residual
+    double alpha;
+    double beta;
+    double tt;        // ||M^dag p||^2
+    double chichi;    // ||chi||^2
+    double true_rr;   // ||chi - A x_hi||^2 at the last reliable update
+    double tol2;      // tol^2 * ||chi||^2
+    double rec_rr;    // iterated ||r||^2 just before the last reliable update
+    int32_t active;   // 1 while this right-hand side iterates
+    int32_t done;     // 1 once the true residual met tol
+    int32_t iters;
+    int32_t reliable;
+    int32_t nonfinite;
+    int32_t pad;
+};
+
+}  // namespace hub
+
+struct hub_ctx {
+    int device = 0;
+    int L = 0, Nt = 0, V = 0, nrhs_max = 0;
+    long long N = 0;                 // V * Nt
+    double beta = 0, kappa = 0, delta = 0;
+    int path = HUB_PATH_FUSED;
+    int lds_fused64 = 0, lds_fused32 = 0;
+    int max_lds = 0;
+    hub::FftPlan plan{};
+
+    // tables
+    double* roots64 = nullptr;   // [L][2]
+    float* roots32 = nullptr;
+    double* etab64 = nullptr;    // [L*L][4]
+    float* etab32 = nullptr;
+
+    // reductions
+    double* partials = nullptr;          // [nrhs_max * max_blocks_per_rhs]
+    int max_partials = 0;
+    unsigned int* counters = nullptr;    // [kNumCounters]
+    double* red_out = nullptr;           // scratch scalar outputs
+
+    // split-path workspace: one complex vector per right-hand side
+    void* split_w = nullptr;             // complex128 [nrhs_max][N] (reused as complex64)
+
+    // CG workspace (allocated on first solve)
+    bool cg_ready = false;
+    void* cg_xhi = nullptr;      // complex128 (when use_x0 == 0 the user's x is used directly)
+    void* cg_rhi = nullptr;      // complex128
+    void* cg_tmp = nullptr;      // complex128 (M^dag x_hi)
+    void* cg_x = nullptr;        // complex128 (FP64 mode) or complex64 (mixed)
+    void* cg_r = nullptr;
+    void* cg_p = nullptr;
+    void* cg_t = nullptr;
+    float* phi32 = nullptr;      // [Nt][V]
+    hub::CgScalars* scal = nullptr;      // device [nrhs_max]
+    hub::CgScalars* scal_host = nullptr; // pinned host mirror
+    double* force_tmp = nullptr;         // [nrhs_max][N] doubles, per-rhs force before summation
+};

@@ -1,0 +1,577 @@
+// Device kernels of the hot path: the operator kernels (fused one-slice-per-workgroup
+// layout and the three-kernel split layout for slices larger than LDS), the
+// source/epilogue functors that specialise them into M, M^dag, the CG steps, the
+// reliable update and the force, and the deterministic last-block reductions.
+#pragma once
+
+#include "hub_fft.hpp"
+
+namespace hub {
+
+constexpr int kThreads = 256;
+
+// Tables and sizes every operator kernel needs.
+template <typename R>
+struct OpTab {
+    const cx<R>* roots;   // [L]
+    const R* etab;        // [L*L][4]
+    FftPlan plan;
+    int L, V, Nt;
+    long long N;
+};
+
+// Reduction plumbing shared by all kernels that reduce.
+struct RedArgs {
+    double* partials;        // [nrhs][slots]
+    unsigned int* counter;
+    int slots;               // partial slots per right-hand side
+    int nrhs;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide sum in a fixed order (result valid in thread 0).
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += lds[w];
+    }
+    return s;
+}
+
+// Store this block's partial, and let the block that arrives last sum every right-hand
+// side's partials in slot order and call fin(rhs, sum).  Deterministic: the final sums
+// never depend on arrival order.  `lds` needs 64 doubles.
+template <class Fin>
+__device__ __forceinline__ void reduce_and_finalize(double acc, int rhs, int slot, const RedArgs& ra,
+                                                    const Fin& fin, double* lds) {
+    __shared__ int is_last;
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&ra.partials[(long long)rhs * ra.slots + slot], s, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(ra.counter, 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (prev == gridDim.x * gridDim.y * gridDim.z - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    for (int r = 0; r < ra.nrhs; ++r) {
+        double v = 0.0;
+        for (int j = threadIdx.x; j < ra.slots; j += blockDim.x)
+            v += __hip_atomic_load(&ra.partials[(long long)r * ra.slots + j], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        const double tot = block_sum(v, lds);
+        if (threadIdx.x == 0) fin(r, tot);
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(ra.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ----------------------------------------------------------------------------- gating
+// CG kernels skip right-hand sides that are not iterating; gating is uniform per block.
+enum Gate : int { GATE_NONE = 0, GATE_ACTIVE = 1, GATE_NOTDONE = 2 };
+
+__device__ __forceinline__ bool gate_open(const CgScalars* sc, int gate, int rhs) {
+    if (gate == GATE_NONE) return true;
+    if (gate == GATE_ACTIVE) return sc[rhs].active != 0;
+    return sc[rhs].done == 0;
+}
+
+// ----------------------------------------------------------------------------- phases
+__device__ __forceinline__ void sincos_r(double a, double* s, double* c) { sincos(a, s, c); }
+__device__ __forceinline__ void sincos_r(float a, float* s, float* c) { sincosf(a, s, c); }
+
+template <typename R>
+__device__ __forceinline__ cx<R> phase(const R* phi, long long idx) {
+    R s, c;
+    sincos_r(phi[idx], &s, &c);
+    return {c, s};
+}
+
+__device__ __forceinline__ int prev_slice(int t, int Nt) { return t == 0 ? Nt - 1 : t - 1; }
+__device__ __forceinline__ int next_slice(int t, int Nt) { return t == Nt - 1 ? 0 : t + 1; }
+
+// ----------------------------------------------------------------------------- sources
+// A source functor names the slice that feeds destination slice t and loads its
+// entries (before E acts).
+template <typename R>
+struct SrcPhasePrev {            // e^{i phi_{t-1}} v_{t-1}            (M)
+    const cx<R>* v;
+    const R* phi;
+    __device__ int slice(int t, int Nt) const { return prev_slice(t, Nt); }
+    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+        const long long k = (long long)ts * T.V + i;
+        return cmul(v[rhs * T.N + k], phase(phi, k));
+    }
+};
+
+template <typename R>
+struct SrcNext {                 // v_{t+1}                            (M^dag, force)
+    const cx<R>* v;
+    __device__ int slice(int t, int Nt) const { return next_slice(t, Nt); }
+    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+        return v[rhs * T.N + (long long)ts * T.V + i];
+    }
+};
+
+template <typename R>
+struct SrcSearchNext {           // (r + beta p)_{t+1}                 (CG: M^dag of the new direction)
+    const cx<R>* r;
+    const cx<R>* p;
+    const CgScalars* sc;
+    __device__ int slice(int t, int Nt) const { return next_slice(t, Nt); }
+    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+        const long long k = rhs * T.N + (long long)ts * T.V + i;
+        const R b = (R)sc[rhs].beta;
+        const cx<R> rv = r[k], pv = p[k];
+        return {rv.re + b * pv.re, rv.im + b * pv.im};
+    }
+};
+
+// ----------------------------------------------------------------------------- epilogues
+// An epilogue functor receives w = (E src)_{t,i} for destination slice t and site i,
+// writes its outputs and adds its contribution to the block's reduction.
+template <typename R>
+struct EpiM {                    // out_t = v_t - B_t w
+    const cx<R>* v;
+    cx<R>* out;
+    __device__ void operator()(int rhs, int t, int i, cx<R> w, const OpTab<R>& T, double&) const {
+        const long long k = rhs * T.N + (long long)t * T.V + i;
+        const cx<R> a = v[k];
+        out[k] = (t == 0) ? a + w : a - w;
+    }
+};
+
+template <typename R>
+struct EpiMdag {                 // out_t = v_t - B_{t+1} e^{-i phi_t} w
+    const cx<R>* v;
+    cx<R>* out;
+    const R* phi;
+    __device__ void operator()(int rhs, int t, int i, cx<R> w, const OpTab<R>& T, double&) const {
+        const long long ks = (long long)t * T.V + i;
+        const long long k = rhs * T.N + ks;
+        const cx<R> pw = cmulc(w, phase(phi, ks));
+        const cx<R> a = v[k];
+        out[k] = (t == T.Nt - 1) ? a + pw : a - pw;
+    }
+};
+
+template <typename R>
+struct EpiSearchMdag {           // CG: tv_t = (r + beta p)_t - B_{t+1} e^{-i phi_t} w ; acc |tv|^2
+    const cx<R>* r;
+    const cx<R>* p;
+    cx<R>* tv;
+    const R* phi;
+    const CgScalars* sc;
+    __device__ void operator()(int rhs, int t, int i, cx<R> w, const OpTab<R>& T, double& acc) const {
+        const long long ks = (long long)t * T.V + i;
+        const long long k = rhs * T.N + ks;
+        const R b = (R)sc[rhs].beta;
+        const cx<R> rv = r[k], pv = p[k];
+        const cx<R> pn = {rv.re + b * pv.re, rv.im + b * pv.im};
+        const cx<R> pw = cmulc(w, phase(phi, ks));
+        const cx<R> o = (t == T.Nt - 1) ? pn + pw : pn - pw;
+        tv[k] = o;
+        acc += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+    }
+};
+
+template <typename R>
+struct EpiUpdate {               // CG: q = tv_t - B_t w; p = r + beta p; x += alpha p; r -= alpha q; acc |r|^2
+    const cx<R>* tv;
+    cx<R>* p;
+    cx<R>* x;
+    cx<R>* r;
+    const CgScalars* sc;
+    __device__ void operator()(int rhs, int t, int i, cx<R> w, const OpTab<R>& T, double& acc) const {
+        const long long k = rhs * T.N + (long long)t * T.V + i;
+        const R b = (R)sc[rhs].beta;
+        const R a = (R)sc[rhs].alpha;
+        const cx<R> tq = tv[k];
+        const cx<R> q = (t == 0) ? tq + w : tq - w;
+        const cx<R> rv = r[k], pv = p[k], xv = x[k];
+        const cx<R> pn = {rv.re + b * pv.re, rv.im + b * pv.im};
+        const cx<R> rn = {rv.re - a * q.re, rv.im - a * q.im};
+        p[k] = pn;
+        x[k] = {xv.re + a * pn.re, xv.im + a * pn.im};
+        r[k] = rn;
+        acc += (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
+    }
+};
+
+template <typename Rlo>
+struct EpiResidual {             // FP64: r_hi = chi - (y_t - B_t w) with y = M^dag x_hi; r_lo = r_hi; acc |r_hi|^2
+    const cx<double>* y;
+    const cx<double>* chi;
+    cx<double>* rhi;
+    cx<Rlo>* rlo;
+    __device__ void operator()(int rhs, int t, int i, cx<double> w, const OpTab<double>& T, double& acc) const {
+        const long long k = rhs * T.N + (long long)t * T.V + i;
+        const cx<double> yv = y[k];
+        const cx<double> q = (t == 0) ? yv + w : yv - w;
+        const cx<double> rv = chi[k] - q;
+        rhi[k] = rv;
+        rlo[k] = {(Rlo)rv.re, (Rlo)rv.im};
+        acc += rv.re * rv.re + rv.im * rv.im;
+    }
+};
+
+struct EpiForce {                // g_t = -2 B_{t+1} Im(e^{i phi_t} x_t conj(w)),  w = (E x_{t+1})
+    const cx<double>* x;
+    const double* phi;
+    double* g;                   // [nrhs or 1][Nt][V]
+    long long g_rhs_stride;      // 0 when there is one right-hand side
+    __device__ void operator()(int rhs, int t, int i, cx<double> w, const OpTab<double>& T, double&) const {
+        const long long ks = (long long)t * T.V + i;
+        const cx<double> z = cmulc(cmul(x[rhs * T.N + ks], phase(phi, ks)), w);
+        const double bn = (t == T.Nt - 1) ? -1.0 : 1.0;
+        g[rhs * g_rhs_stride + ks] = -2.0 * bn * z.im;
+    }
+};
+
+// ----------------------------------------------------------------------------- finalizers
+struct FinNone {
+    static constexpr bool kReduce = false;
+    __device__ void operator()(int, double) const {}
+};
+
+struct FinSearch {               // alpha = rr / ||M^dag p||^2
+    static constexpr bool kReduce = true;
+    CgScalars* sc;
+    __device__ void operator()(int r, double tt) const {
+        if (!sc[r].active) return;
+        sc[r].tt = tt;
+        const double a = sc[r].rr / tt;
+        if (!(tt > 0.0) || !isfinite(a)) {
+            sc[r].nonfinite = 1;
+            sc[r].active = 0;
+            return;
+        }
+        sc[r].alpha = a;
+    }
+};
+
+struct FinUpdate {               // beta = rr'/rr; stop iterating once the iterated residual meets tol
+    static constexpr bool kReduce = true;
+    CgScalars* sc;
+    __device__ void operator()(int r, double rr) const {
+        if (!sc[r].active) return;
+        sc[r].iters += 1;
+        if (!isfinite(rr)) {
+            sc[r].nonfinite = 1;
+            sc[r].active = 0;
+            return;
+        }
+        sc[r].beta = rr / sc[r].rr;
+        sc[r].rr = rr;
+        if (rr <= sc[r].tol2) sc[r].active = 0;
+    }
+};
+
+struct FinResidual {             // after an FP64 residual recomputation
+    static constexpr bool kReduce = true;
+    CgScalars* sc;
+    __device__ void operator()(int r, double rr) const {
+        if (sc[r].done) return;
+        sc[r].reliable += 1;
+        sc[r].rec_rr = sc[r].rr;
+        sc[r].true_rr = rr;
+        if (!isfinite(rr)) {
+            sc[r].nonfinite = 1;
+            sc[r].active = 0;
+            return;
+        }
+        sc[r].rr = rr;
+        if (rr <= sc[r].tol2) {
+            sc[r].done = 1;
+            sc[r].active = 0;
+        } else if (!sc[r].nonfinite) {
+            sc[r].active = 1;
+        }
+    }
+};
+
+struct FinInit {                 // ||chi||^2 and the starting state of every right-hand side
+    static constexpr bool kReduce = true;
+    CgScalars* sc;
+    double tol;
+    int start_from_zero;
+    __device__ void operator()(int r, double cc) const {
+        CgScalars s{};
+        s.chichi = cc;
+        s.tol2 = tol * tol * cc;
+        s.rr = cc;
+        s.true_rr = cc;
+        s.rec_rr = cc;
+        s.beta = 0.0;
+        s.alpha = 0.0;
+        s.nonfinite = isfinite(cc) ? 0 : 1;
+        s.done = (cc == 0.0) ? 1 : 0;
+        s.active = (start_from_zero && !s.done && !s.nonfinite) ? 1 : 0;
+        sc[r] = s;
+    }
+};
+
+struct FinStore {                // out[0] = sum over right-hand sides (in order)
+    static constexpr bool kReduce = true;
+    double* out;
+    int nrhs;
+    __device__ void operator()(int r, double v) const {
+        // called for r = 0..nrhs-1 in order by one thread
+        out[0] = (r == 0) ? v : out[0] + v;
+    }
+};
+
+// ----------------------------------------------------------------------------- fused kernel
+// One workgroup per (right-hand side, destination slice): the source slice lives in
+// LDS, both sublattices are transformed, mixed by E(k) and transformed back, and the
+// epilogue streams the result out.  Block -> slice mapping keeps consecutive slices on
+// one XCD (workgroups are dealt round-robin over the 8 XCDs), so the neighbouring
+// slice that an epilogue and the next workgroup's source share hits the same L2.
+__device__ __forceinline__ int xcd_linear(int b, int total) {
+    const int x = b & 7, j = b >> 3;
+    const int per = total >> 3, rem = total & 7;
+    return x * per + (x < rem ? x : rem) + j;
+}
+
+template <typename R>
+__device__ __forceinline__ void mix_E(cx<R>* A, cx<R>* B, int LL, const R* __restrict__ etab) {
+    for (int p = threadIdx.x; p < LL; p += blockDim.x) {
+        const R c = etab[4 * p], sr = etab[4 * p + 1], si = etab[4 * p + 2];
+        const cx<R> a = A[p], b = B[p];
+        // A' = c a + sf b ;  B' = conj(sf) a + c b
+        A[p] = {c * a.re + sr * b.re - si * b.im, c * a.im + sr * b.im + si * b.re};
+        B[p] = {c * b.re + sr * a.re + si * a.im, c * b.im + sr * a.im - si * a.re};
+    }
+}
+
+template <typename R, class Src, class Epi, class Fin>
+__global__ void __launch_bounds__(kThreads)
+k_fused(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const RedArgs ra,
+        const CgScalars* sc, int gate) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    cx<R>* roots = buf + T.V;
+    const int L = T.L, LL = L * L, V = T.V;
+    const int u = xcd_linear(blockIdx.x, gridDim.x);
+    const int rhs = u / T.Nt, t = u - rhs * T.Nt;
+    double acc = 0.0;
+    if (gate_open(sc, gate, rhs)) {
+        for (int i = threadIdx.x; i < L; i += blockDim.x) roots[i] = T.roots[i];
+        const int ts = src.slice(t, T.Nt);
+        for (int i = threadIdx.x; i < V; i += blockDim.x) buf[i] = src(rhs, ts, i, T);
+        __syncthreads();
+        const LineMap rows{1, L, 0, 1};
+        const LineMap cols{L, LL, 1, L};
+        fft_lines<R, false>(buf, rows, 2 * L, T.plan, roots);
+        fft_lines<R, false>(buf, cols, 2 * L, T.plan, roots);
+        mix_E(buf, buf + LL, LL, T.etab);
+        __syncthreads();
+        fft_lines<R, true>(buf, cols, 2 * L, T.plan, roots);
+        fft_lines<R, true>(buf, rows, 2 * L, T.plan, roots);
+        for (int i = threadIdx.x; i < V; i += blockDim.x) epi(rhs, t, i, buf[i], T, acc);
+    }
+    if constexpr (Fin::kReduce) reduce_and_finalize(acc, rhs, t, ra, fin, red_lds);
+}
+
+// ----------------------------------------------------------------------------- split kernels
+// Slices too large for LDS: (1) row transforms of the source slice into a scratch
+// vector W, (2) column transforms + E(k) + inverse column transforms of W in place,
+// (3) inverse row transforms of W and the epilogue.  W is indexed by destination slice.
+struct SplitGeom {
+    int rb, nrb;      // rows per block, row blocks per sublattice
+    int cb, ncb;      // columns per block, column blocks
+};
+
+template <typename R, class Src>
+__global__ void __launch_bounds__(kThreads)
+k_split_rows_fwd(const OpTab<R> T, const SplitGeom G, const Src src, cx<R>* __restrict__ W,
+                 const CgScalars* sc, int gate) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    const int L = T.L;
+    cx<R>* roots = buf + G.rb * L;
+    int b = blockIdx.x;
+    const int rblk = b % G.nrb; b /= G.nrb;
+    const int s = b % 2; b /= 2;
+    const int t = b % T.Nt;
+    const int rhs = b / T.Nt;
+    if (!gate_open(sc, gate, rhs)) return;
+    const int r0 = rblk * G.rb;
+    const int nr = min(G.rb, L - r0);
+    for (int i = threadIdx.x; i < L; i += blockDim.x) roots[i] = T.roots[i];
+    const int ts = src.slice(t, T.Nt);
+    const int off = s * L * L + r0 * L;
+    for (int i = threadIdx.x; i < nr * L; i += blockDim.x) buf[i] = src(rhs, ts, off + i, T);
+    __syncthreads();
+    fft_lines<R, false>(buf, LineMap{1, L, 0, 1}, nr, T.plan, roots);
+    cx<R>* dst = W + rhs * T.N + (long long)t * T.V + off;
+    for (int i = threadIdx.x; i < nr * L; i += blockDim.x) dst[i] = buf[i];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_split_cols(const OpTab<R> T, const SplitGeom G, cx<R>* __restrict__ W, const CgScalars* sc, int gate) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    const int L = T.L, LL = L * L;
+    cx<R>* roots = buf + 2 * L * G.cb;
+    int b = blockIdx.x;
+    const int cblk = b % G.ncb; b /= G.ncb;
+    const int t = b % T.Nt;
+    const int rhs = b / T.Nt;
+    if (!gate_open(sc, gate, rhs)) return;
+    const int c0 = cblk * G.cb;
+    const int nc = min(G.cb, L - c0);
+    for (int i = threadIdx.x; i < L; i += blockDim.x) roots[i] = T.roots[i];
+    cx<R>* base = W + rhs * T.N + (long long)t * T.V;
+    // LDS tile [s][n1][c], c fastest
+    for (int i = threadIdx.x; i < 2 * L * nc; i += blockDim.x) {
+        const int c = i % nc, sn = i / nc;           // sn = s*L + n1
+        buf[i] = base[(long long)sn * L + c0 + c];
+    }
+    __syncthreads();
+    const LineMap cols{nc, L * nc, 1, nc};
+    fft_lines<R, false>(buf, cols, 2 * nc, T.plan, roots);
+    for (int i = threadIdx.x; i < L * nc; i += blockDim.x) {
+        const int c = i % nc, n1 = i / nc;
+        const int p = n1 * L + c0 + c;
+        const R cc = T.etab[4 * p], sr = T.etab[4 * p + 1], si = T.etab[4 * p + 2];
+        const cx<R> a = buf[i], bb = buf[L * nc + i];
+        buf[i] = {cc * a.re + sr * bb.re - si * bb.im, cc * a.im + sr * bb.im + si * bb.re};
+        buf[L * nc + i] = {cc * bb.re + sr * a.re + si * a.im, cc * bb.im + sr * a.im - si * a.re};
+    }
+    __syncthreads();
+    fft_lines<R, true>(buf, cols, 2 * nc, T.plan, roots);
+    for (int i = threadIdx.x; i < 2 * L * nc; i += blockDim.x) {
+        const int c = i % nc, sn = i / nc;
+        base[(long long)sn * L + c0 + c] = buf[i];
+    }
+    (void)LL;
+}
+
+template <typename R, class Epi, class Fin>
+__global__ void __launch_bounds__(kThreads)
+k_split_rows_inv(const OpTab<R> T, const SplitGeom G, const cx<R>* __restrict__ W, const Epi epi,
+                 const Fin fin, const RedArgs ra, const CgScalars* sc, int gate) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    const int L = T.L;
+    cx<R>* roots = buf + G.rb * L;
+    int b = blockIdx.x;
+    const int slot = b % (2 * G.nrb * T.Nt);
+    const int rblk = b % G.nrb; b /= G.nrb;
+    const int s = b % 2; b /= 2;
+    const int t = b % T.Nt;
+    const int rhs = b / T.Nt;
+    double acc = 0.0;
+    if (gate_open(sc, gate, rhs)) {
+        const int r0 = rblk * G.rb;
+        const int nr = min(G.rb, L - r0);
+        for (int i = threadIdx.x; i < L; i += blockDim.x) roots[i] = T.roots[i];
+        const int off = s * L * L + r0 * L;
+        const cx<R>* srcp = W + rhs * T.N + (long long)t * T.V + off;
+        for (int i = threadIdx.x; i < nr * L; i += blockDim.x) buf[i] = srcp[i];
+        __syncthreads();
+        fft_lines<R, true>(buf, LineMap{1, L, 0, 1}, nr, T.plan, roots);
+        for (int i = threadIdx.x; i < nr * L; i += blockDim.x) epi(rhs, t, off + i, buf[i], T, acc);
+    }
+    if constexpr (Fin::kReduce) reduce_and_finalize(acc, rhs, slot, ra, fin, red_lds);
+}
+
+// ----------------------------------------------------------------------------- elementwise kernels
+// One block per (right-hand side, slice); reductions in slice order.
+template <typename Rlo>
+__global__ void __launch_bounds__(kThreads)
+k_cg_init(const cx<double>* __restrict__ chi, cx<double>* __restrict__ xhi, cx<double>* __restrict__ rhi,
+          cx<Rlo>* __restrict__ xlo, cx<Rlo>* __restrict__ rlo, cx<Rlo>* __restrict__ p, int V, int Nt,
+          int zero_start, FinInit fin, RedArgs ra) {
+    __shared__ double red_lds[64];
+    const int t = blockIdx.x % Nt, rhs = blockIdx.x / Nt;
+    const long long base = (long long)rhs * V * Nt + (long long)t * V;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < V; i += blockDim.x) {
+        const long long k = base + i;
+        const cx<double> c = chi[k];
+        acc += c.re * c.re + c.im * c.im;
+        xlo[k] = {(Rlo)0, (Rlo)0};
+        p[k] = {(Rlo)0, (Rlo)0};
+        if (zero_start) {
+            xhi[k] = {0.0, 0.0};
+            rhi[k] = c;
+            rlo[k] = {(Rlo)c.re, (Rlo)c.im};
+        }
+    }
+    reduce_and_finalize(acc, rhs, t, ra, fin, red_lds);
+}
+
+template <typename Rlo>
+__global__ void __launch_bounds__(kThreads)
+k_fold_solution(cx<double>* __restrict__ xhi, cx<Rlo>* __restrict__ xlo, int V, int Nt,
+                const CgScalars* sc) {
+    const int t = blockIdx.x % Nt, rhs = blockIdx.x / Nt;
+    if (sc[rhs].done) return;
+    const long long base = (long long)rhs * V * Nt + (long long)t * V;
+    for (int i = threadIdx.x; i < V; i += blockDim.x) {
+        const long long k = base + i;
+        const cx<Rlo> a = xlo[k];
+        const cx<double> h = xhi[k];
+        xhi[k] = {h.re + (double)a.re, h.im + (double)a.im};
+        xlo[k] = {(Rlo)0, (Rlo)0};
+    }
+}
+
+// x = 0 for right-hand sides whose chi is zero (their exact solution)
+__global__ void __launch_bounds__(kThreads)
+k_zero_trivial(cx<double>* __restrict__ xhi, int V, int Nt, const CgScalars* sc) {
+    const int t = blockIdx.x % Nt, rhs = blockIdx.x / Nt;
+    if (sc[rhs].chichi != 0.0) return;
+    const long long base = (long long)rhs * V * Nt + (long long)t * V;
+    for (int i = threadIdx.x; i < V; i += blockDim.x) xhi[base + i] = {0.0, 0.0};
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_dot_re(const cx<double>* __restrict__ a, const cx<double>* __restrict__ b, int V, int Nt,
+         FinStore fin, RedArgs ra) {
+    __shared__ double red_lds[64];
+    const int t = blockIdx.x % Nt, rhs = blockIdx.x / Nt;
+    const long long base = (long long)rhs * V * Nt + (long long)t * V;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < V; i += blockDim.x) {
+        const cx<double> x = a[base + i], y = b[base + i];
+        acc += x.re * y.re + x.im * y.im;
+    }
+    reduce_and_finalize(acc, rhs, t, ra, fin, red_lds);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_sum_rhs(const double* __restrict__ parts, double* __restrict__ g, long long n, int nrhs) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double s = parts[i];
+        for (int r = 1; r < nrhs; ++r) s += parts[r * n + i];
+        g[i] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_to_float(const double* __restrict__ a, float* __restrict__ b, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+}  // namespace hub

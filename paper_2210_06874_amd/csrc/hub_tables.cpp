@@ -1,0 +1,91 @@
+// Host-side FP64 tables: mixed-radix plan, DFT roots of unity and the momentum-space
+// hopping exponential E(k) = exp(delta*kappa*K(k)) of the honeycomb torus.
+//
+// In momentum space (Bloch theorem on the L x L torus) the hopping matrix of the
+// honeycomb lattice (paper Sec. 1, fig. "honeycomb_lattice") is the 2 x 2 block
+// K(k) = [[0, f(k)], [conj f(k), 0]], f(k) = 1 + e^{-i k1} + e^{-i k2}, whose
+// eigenvalues +-|f(k)| are the two free bands of Sec. 1.  Because K(k)^2 = |f|^2,
+//     exp(dk K(k)) = cosh(dk|f|) 1 + sinh(dk|f|)/|f| K(k).
+#include <cmath>
+
+#include "hub_internal.hpp"
+
+namespace hub {
+
+static const int kRadices[] = {4, 2, 3, 5, 7, 11, 13, 17};
+
+bool make_plan(int L, FftPlan* plan) {
+    if (L < 1 || L > 1024) return false;
+    plan->L = L;
+    plan->nst = 0;
+    int rest = L;
+    // Extract factors of 4 first, then the other supported primes.
+    for (int r : kRadices) {
+        while (rest % r == 0) {
+            if (plan->nst >= kMaxStages) return false;
+            plan->radix[plan->nst++] = r;
+            rest /= r;
+        }
+    }
+    if (rest != 1) return false;
+    int len = L;
+    for (int q = 0; q < plan->nst; ++q) {
+        plan->len[q] = len;
+        len /= plan->radix[q];
+    }
+    return true;
+}
+
+int digit_reversed_position(const FftPlan& plan, int k) {
+    // k = k_0 + r_0 k_1 + r_0 r_1 k_2 + ...; after stage q the digit k_q sits at
+    // stride len[q] / radix[q] inside its block.
+    int pos = 0;
+    for (int q = 0; q < plan.nst; ++q) {
+        const int r = plan.radix[q];
+        pos += (k % r) * (plan.len[q] / r);
+        k /= r;
+    }
+    return pos;
+}
+
+void build_tables(const FftPlan& plan, double dk, std::vector<double>& roots,
+                  std::vector<double>& etab) {
+    const int L = plan.L;
+    const double two_pi = 6.283185307179586476925286766559;
+    roots.assign(2 * (size_t)L, 0.0);
+    for (int m = 0; m < L; ++m) {
+        const double a = two_pi * (double)m / (double)L;   // m < L: exact integer numerator
+        roots[2 * m] = std::cos(a);
+        roots[2 * m + 1] = -std::sin(a);
+    }
+    std::vector<int> inv_pos(L);
+    for (int k = 0; k < L; ++k) inv_pos[digit_reversed_position(plan, k)] = k;
+    etab.assign(4 * (size_t)L * L, 0.0);
+    const double norm = 1.0 / ((double)L * (double)L);
+    for (int p1 = 0; p1 < L; ++p1) {
+        const int k1 = inv_pos[p1];
+        for (int p2 = 0; p2 < L; ++p2) {
+            const int k2 = inv_pos[p2];
+            const double fr = 1.0 + roots[2 * k1] + roots[2 * k2];
+            const double fi = roots[2 * k1 + 1] + roots[2 * k2 + 1];
+            const double af = std::hypot(fr, fi);
+            const double x = dk * af;
+            const double c = std::cosh(x);
+            double s;
+            if (x < 1e-4) {
+                // sinh(x)/x series; |f| may vanish exactly at the Dirac momenta
+                const double x2 = x * x;
+                s = dk * (1.0 + x2 / 6.0 * (1.0 + x2 / 20.0));
+            } else {
+                s = std::sinh(x) / af;
+            }
+            double* e = &etab[4 * ((size_t)p1 * L + p2)];
+            e[0] = c * norm;
+            e[1] = s * fr * norm;
+            e[2] = s * fi * norm;
+            e[3] = 0.0;
+        }
+    }
+}
+
+}  // namespace hub

@@ -1,0 +1,157 @@
+"""GPU parity of the fermion operator kernels (hub_apply_M / hub_apply_Mdag and their
+FP32 variants) against the FP64 CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from workloads import TINY, SMALL, DIFF, PREC, STRESS, Lattice, draw_inputs, draw_complex
+from gpu_common import dev, to_dev, to_np, oracle_op, assert_close_elementwise
+import closed_forms as CF
+
+pytestmark = pytest.mark.gpu
+
+RTOL64 = 1e-12     # FP64: transform roundoff ~ (stages) * 2^-53 relative to the largest entry
+RTOL32 = 2e-5      # FP32: the same arithmetic at 2^-24
+
+
+def _hub(w, path="auto", nrhs=1):
+    from paper_2210_06874_amd import Hubbard
+    return Hubbard(w.L, w.Nt, w.beta, w.kappa, nrhs_max=nrhs, path=path)
+
+
+EDGE = [
+    Lattice("L1_Nt1", 1, 1, 0.5, 3.0), Lattice("L1_Nt2", 1, 2, 1.0, 3.0),
+    Lattice("L2_Nt2", 2, 2, 0.7, 3.0), Lattice("L5_Nt3", 5, 3, 1.5, 3.0),
+    Lattice("L7_Nt4", 7, 4, 2.0, 3.0), Lattice("L10_Nt5", 10, 5, 2.0, 3.0),
+    Lattice("L17_Nt3", 17, 3, 1.0, 3.0), Lattice("L6_Nt9", 6, 9, 3.0, 3.0),
+]
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+@pytest.mark.parametrize("w", [TINY, SMALL] + EDGE, ids=lambda w: w.name)
+def test_apply_fp64_matches_oracle(w, path):
+    print(f"[case] apply fp64 {w.name} path={path}", flush=True)
+    phi, v = draw_inputs(w, seed=11, nrhs=2)
+    hub = _hub(w, path, nrhs=2)
+    assert hub.path == path
+    op = oracle_op(w)
+    got_M = to_np(hub.apply_M(to_dev(phi), to_dev(v)))
+    got_D = to_np(hub.apply_Mdag(to_dev(phi), to_dev(v)))
+    assert_close_elementwise(got_M, op.apply_M(phi, v), RTOL64, "M")
+    assert_close_elementwise(got_D, op.apply_Mdag(phi, v), RTOL64, "Mdag")
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+@pytest.mark.parametrize("w", [TINY, SMALL, EDGE[3], EDGE[6]], ids=lambda w: w.name)
+def test_apply_fp32_matches_oracle(w, path):
+    print(f"[case] apply fp32 {w.name} path={path}", flush=True)
+    phi, v = draw_inputs(w, seed=12)
+    phi32 = phi.astype(np.float32)
+    v64 = v.astype(np.complex64)
+    hub = _hub(w, path)
+    op = oracle_op(w)
+    ref_M = op.apply_M(phi32.astype(np.float64), v64.astype(np.complex128))
+    ref_D = op.apply_Mdag(phi32.astype(np.float64), v64.astype(np.complex128))
+    got_M = to_np(hub.apply_M_c64(to_dev(phi32), to_dev(v64)))
+    got_D = to_np(hub.apply_Mdag_c64(to_dev(phi32), to_dev(v64)))
+    assert_close_elementwise(got_M, ref_M, RTOL32, "M32")
+    assert_close_elementwise(got_D, ref_D, RTOL32, "Mdag32")
+
+
+def test_apply_diff_workload_fp64():
+    w = DIFF
+    print(f"[case] apply fp64 {w.name}", flush=True)
+    phi, v = draw_inputs(w, seed=13)
+    hub = _hub(w)
+    op = oracle_op(w, mode="expm")
+    assert_close_elementwise(to_np(hub.apply_M(to_dev(phi), to_dev(v))), op.apply_M(phi, v), RTOL64, "M")
+    assert_close_elementwise(to_np(hub.apply_Mdag(to_dev(phi), to_dev(v))), op.apply_Mdag(phi, v), RTOL64, "Mdag")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_precision_workload(prec):
+    """L = 51, Nt = 128: the full operator against the oracle's Krylov-exp route."""
+    w = PREC
+    print(f"[case] apply {prec} {w.name}", flush=True)
+    phi, v = draw_inputs(w, seed=14)
+    hub = _hub(w)
+    op = oracle_op(w, mode="expm")
+    if prec == "fp64":
+        got = to_np(hub.apply_M(to_dev(phi), to_dev(v)))
+        assert_close_elementwise(got, op.apply_M(phi, v), RTOL64, "M")
+        got = to_np(hub.apply_Mdag(to_dev(phi), to_dev(v)))
+        assert_close_elementwise(got, op.apply_Mdag(phi, v), RTOL64, "Mdag")
+    else:
+        p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
+        got = to_np(hub.apply_M_c64(to_dev(p32), to_dev(v32)))
+        ref = op.apply_M(p32.astype(np.float64), v32.astype(np.complex128))
+        assert_close_elementwise(got, ref, RTOL32, "M32")
+
+
+def _stress_slices(op, phi, v, slices, dagger):
+    """Oracle rows of M v (or M^dag v) for a few destination slices only."""
+    out = {}
+    for t in slices:
+        if not dagger:
+            ts = (t - 1) % op.Nt
+            src = np.exp(1j * phi[ts])[None] * v[:, ts]
+            hop = op.apply_E(src)
+            out[t] = v[:, t] - op.B[t] * hop
+        else:
+            ts = (t + 1) % op.Nt
+            hop = op.apply_E(v[:, ts])
+            out[t] = v[:, t] - op.B[ts] * np.exp(-1j * phi[t])[None] * hop
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_stress_workload_sampled(prec):
+    """L = 102, Nt = 192, 4 right-hand sides in one call (split path): sampled slices,
+    including both wrap slices, against the oracle."""
+    w = STRESS
+    print(f"[case] apply {prec} {w.name}", flush=True)
+    phi, v = draw_inputs(w, seed=15)
+    hub = _hub(w, nrhs=4)
+    op = oracle_op(w, mode="expm")
+    slices = [0, 1, 77, w.Nt - 1]
+    if prec == "fp32":
+        phi = phi.astype(np.float32).astype(np.float64)
+        v = v.astype(np.complex64).astype(np.complex128)
+        gM = to_np(hub.apply_M_c64(to_dev(phi.astype(np.float32)), to_dev(v.astype(np.complex64))))
+        gD = to_np(hub.apply_Mdag_c64(to_dev(phi.astype(np.float32)), to_dev(v.astype(np.complex64))))
+        tol = RTOL32
+    else:
+        gM = to_np(hub.apply_M(to_dev(phi), to_dev(v)))
+        gD = to_np(hub.apply_Mdag(to_dev(phi), to_dev(v)))
+        tol = RTOL64
+    for dag, got in ((False, gM), (True, gD)):
+        ref = _stress_slices(op, phi, v, slices, dag)
+        for t in slices:
+            assert_close_elementwise(got[:, t], ref[t], tol, f"slice {t} dag={dag}")
+
+
+@pytest.mark.parametrize("w", [PREC, STRESS], ids=lambda w: w.name)
+def test_adjointness_at_scale(w):
+    """<u, M v> = <M^dag u, v> on the GPU at full size (P6)."""
+    print(f"[case] adjointness {w.name}", flush=True)
+    phi, u = draw_inputs(w, seed=16)
+    vv = draw_complex(w, seed=17)
+    hub = _hub(w, nrhs=w.nrhs)
+    P, U, Vv = to_dev(phi), to_dev(u), to_dev(vv)
+    a = torch.vdot(U.flatten(), hub.apply_M(P, Vv).flatten()).item()
+    b = torch.vdot(hub.apply_Mdag(P, U).flatten(), Vv.flatten()).item()
+    assert abs(a - b) <= 1e-11 * abs(a)
+
+
+@pytest.mark.parametrize("w", [PREC, STRESS], ids=lambda w: w.name)
+def test_free_plane_waves_at_scale(w):
+    """phi = 0: plane waves are eigenvectors with eigenvalue 1 - e^{-i omega} e^{delta eps} (P2)."""
+    print(f"[case] plane waves {w.name}", flush=True)
+    hub = _hub(w)
+    phi = torch.zeros((w.Nt, w.V), dtype=torch.float64, device=dev())
+    for (n, m1, m2, band) in [(0, 0, 0, 1), (w.Nt - 1, w.L // 3, 2 * w.L // 3, -1), (5, 7, 11, 1)]:
+        v, eps, om = CF.plane_wave(w.L, w.Nt, n, m1, m2, band)
+        lam = CF.free_M_eigenvalue(eps, om, w.delta)
+        got = to_np(hub.apply_M(phi, to_dev(v)))
+        assert_close_elementwise(got, lam * v, RTOL64, f"plane wave {n},{m1},{m2}")

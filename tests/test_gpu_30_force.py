@@ -1,0 +1,92 @@
+"""GPU parity of the pseudofermion force hub_force and the autograd binding."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from workloads import TINY, SMALL, DIFF_SUB, PREC, draw_inputs, draw_complex
+from gpu_common import dev, to_dev, to_np, oracle_op, assert_close_elementwise
+
+pytestmark = pytest.mark.gpu
+
+
+def _hub(w, nrhs=1, path="auto"):
+    from paper_2210_06874_amd import Hubbard
+    return Hubbard(w.L, w.Nt, w.beta, w.kappa, nrhs_max=nrhs, path=path)
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+@pytest.mark.parametrize("w", [TINY, DIFF_SUB, SMALL], ids=lambda w: w.name)
+def test_force_kernel_matches_oracle_from_same_x(w, path):
+    """hub_force(x) against the oracle's force from the same x (kernel alone)."""
+    print(f"[case] force {w.name} {path}", flush=True)
+    phi, x = draw_inputs(w, seed=21, nrhs=2)
+    hub = _hub(w, nrhs=2, path=path)
+    op = oracle_op(w)
+    got = to_np(hub.force(to_dev(phi), to_dev(x)))
+    assert_close_elementwise(got, O.force(op, phi, x), 1e-12, "force")
+
+
+def test_force_precision_workload():
+    w = PREC
+    print(f"[case] force {w.name}", flush=True)
+    phi, x = draw_inputs(w, seed=22)
+    hub = _hub(w)
+    op = oracle_op(w, mode="expm")
+    got = to_np(hub.force(to_dev(phi), to_dev(x)))
+    assert_close_elementwise(got, O.force(op, phi, x), 1e-12, "force")
+
+
+def test_force_end_to_end_tiny_dense():
+    """CG + force against the dense-oracle gradient; error bounded by cond * tol."""
+    w = TINY
+    phi, chi = draw_inputs(w)
+    op = oracle_op(w)
+    g_ref = O.force_dense(op, phi, O.dense_solve(op, phi, chi))
+    hub = _hub(w)
+    res = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-13, max_iter=20000)
+    g = to_np(hub.force(to_dev(phi), res.x))
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert err < 1e-8, err
+
+
+def test_autograd_backward_is_force():
+    from paper_2210_06874_amd import PseudofermionAction
+    w = TINY
+    phi, chi = draw_inputs(w)
+    hub = _hub(w)
+    P = to_dev(phi).requires_grad_(True)
+    S = PseudofermionAction.apply(P, to_dev(chi), hub, 1e-12)
+    S.backward()
+    res = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-12)
+    g = hub.force(to_dev(phi), res.x)
+    assert torch.equal(P.grad, g)
+    op = oracle_op(w)
+    x_ref = O.dense_solve(op, phi, chi)
+    assert abs(S.item() - O.action(chi, x_ref)) <= 1e-9 * abs(S.item())
+    # twice the same call: bitwise identical
+    P2 = to_dev(phi).requires_grad_(True)
+    S2 = PseudofermionAction.apply(P2, to_dev(chi), hub, 1e-12)
+    S2.backward()
+    assert S2.item() == S.item() and torch.equal(P2.grad, P.grad)
+
+
+def test_force_gauge_sum_rule_precision_workload():
+    """sum_x g_{s-1,x} - sum_x g_{s,x} = -2 Im(chi_s^dag x_s) (P8) with x = hub's solution
+    of a chi = M rho system on the weak-field L = 51 workload."""
+    from workloads import draw_weak_field
+    w = PREC
+    phi, _ = draw_weak_field(w)
+    rho = draw_complex(w, seed=3)
+    hub = _hub(w)
+    P = to_dev(phi)
+    chi = hub.apply_M(P, to_dev(rho))
+    res = hub.cg_solve(P, chi, tol=1e-12, max_iter=20000)
+    assert res.converged
+    g = to_np(hub.force(P, res.x))
+    x = to_np(res.x)
+    c = to_np(chi)
+    lhs = np.roll(g.sum(axis=1), 1) - g.sum(axis=1)
+    rhs = -2 * np.einsum("rtx,rtx->t", np.conj(c), x).imag
+    scale = np.abs(g).sum(axis=1).max()
+    np.testing.assert_allclose(lhs, rhs, atol=1e-9 * scale)
