@@ -104,25 +104,29 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Fi
     return launch_check("k_split_rows_inv");
 }
 
-bool overlaps(const void* a, const void* b, size_t bytes) {
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
     const char* x = static_cast<const char*>(a);
     const char* y = static_cast<const char*>(b);
-    return x < y + bytes && y < x + bytes;
+    return x < y + bbytes && y < x + abytes;
 }
 
+// in: nrhs vectors of `elem`-byte entries; out: nrhs vectors (out_per_rhs) or one array of
+// N entries of out_elem bytes.
 hub_status check_vec_args(const hub_ctx* c, const void* phi, const void* in, const void* out, int nrhs,
-                          size_t elem) {
+                          size_t elem, size_t out_elem, bool out_per_rhs) {
     if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
     if (!phi || !in || !out) return fail(HUB_ERR_ARG, "NULL array argument");
     if (nrhs < 1 || nrhs > c->nrhs_max)
         return fail(HUB_ERR_ARG, "nrhs=%d outside [1, nrhs_max=%d]", nrhs, c->nrhs_max);
-    if (overlaps(in, out, (size_t)nrhs * c->N * elem)) return fail(HUB_ERR_ARG, "in and out overlap");
+    const size_t in_bytes = (size_t)nrhs * c->N * elem;
+    const size_t out_bytes = (size_t)(out_per_rhs ? nrhs : 1) * c->N * out_elem;
+    if (overlaps(in, in_bytes, out, out_bytes)) return fail(HUB_ERR_ARG, "input and output overlap");
     return HUB_OK;
 }
 
 template <typename R>
 hub_status apply_M_impl(hub_ctx* c, const R* phi, const void* in, void* out, int nrhs, void* stream) {
-    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>));
+    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
     return run_op<R>(c, nrhs, SrcPhasePrev<R>{v, phi}, EpiM<R>{v, static_cast<cx<R>*>(out)}, FinNone{}, 0,
@@ -131,7 +135,7 @@ hub_status apply_M_impl(hub_ctx* c, const R* phi, const void* in, void* out, int
 
 template <typename R>
 hub_status apply_Mdag_impl(hub_ctx* c, const R* phi, const void* in, void* out, int nrhs, void* stream) {
-    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>));
+    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
     return run_op<R>(c, nrhs, SrcNext<R>{v}, EpiMdag<R>{v, static_cast<cx<R>*>(out), phi}, FinNone{}, 0,
@@ -359,7 +363,7 @@ hub_status hub_apply_Mdag_c64(hub_ctx* c, const float* phi, const void* in, void
 
 hub_status hub_cg_solve(hub_ctx* c, const double* phi, const void* chi, void* x, int32_t nrhs,
                         const hub_cg_opts* opts, hub_cg_info* info, void* stream) {
-    hub_status s = check_vec_args(c, phi, chi, x, nrhs, sizeof(cx<double>));
+    hub_status s = check_vec_args(c, phi, chi, x, nrhs, sizeof(cx<double>), sizeof(cx<double>), true);
     if (s != HUB_OK) return s;
     if (!opts) return fail(HUB_ERR_ARG, "opts is NULL");
     if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) return fail(HUB_ERR_ARG, "tol must be > 0");
@@ -377,9 +381,10 @@ hub_status hub_cg_solve(hub_ctx* c, const double* phi, const void* chi, void* x,
 }
 
 hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, int32_t nrhs, void* stream) {
-    hub_status s = check_vec_args(c, phi, x, g, nrhs, sizeof(cx<double>));
+    hub_status s = check_vec_args(c, phi, x, g, nrhs, sizeof(cx<double>), sizeof(double), false);
     if (s != HUB_OK) return s;
-    if (overlaps(g, phi, (size_t)c->N * sizeof(double))) return fail(HUB_ERR_ARG, "dSdphi overlaps phi");
+    if (overlaps(g, (size_t)c->N * sizeof(double), phi, (size_t)c->N * sizeof(double)))
+        return fail(HUB_ERR_ARG, "dSdphi overlaps phi");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const cx<double>* xv = static_cast<const cx<double>*>(x);
     if (nrhs == 1)

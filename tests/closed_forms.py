@@ -46,11 +46,12 @@ def plane_wave(L, Nt, n, m1, m2, band):
         ua, ub = f / af, band * 1.0
         eps = band * af
     n1, n2 = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
-    ph = np.exp(1j * (k1 * n1 + k2 * n2)).ravel()
+    # angles reduced with integer arithmetic, so every phase is accurate to ~1e-16
+    ph = np.exp(2j * np.pi * ((m1 * n1 + m2 * n2) % L) / L).ravel()
     spatial = np.concatenate([ua * ph, ub * ph]) / np.sqrt(2 * L * L)
     omega = (2 * n + 1) * np.pi / Nt
     t = np.arange(Nt)
-    v = np.exp(1j * omega * t)[:, None] * spatial[None, :] / np.sqrt(Nt)
+    v = np.exp(1j * np.pi * (((2 * n + 1) * t) % (2 * Nt)) / Nt)[:, None] * spatial[None, :] / np.sqrt(Nt)
     return v, eps, omega
 
 

@@ -154,4 +154,7 @@ def test_free_plane_waves_at_scale(w):
         v, eps, om = CF.plane_wave(w.L, w.Nt, n, m1, m2, band)
         lam = CF.free_M_eigenvalue(eps, om, w.delta)
         got = to_np(hub.apply_M(phi, to_dev(v)))
-        assert_close_elementwise(got, lam * v, RTOL64, f"plane wave {n},{m1},{m2}")
+        # relative to the input's scale: near omega ~ 2 pi the eigenvalue is small and
+        # M v is a difference of two terms of size |v|
+        err = np.abs(got - lam * v).max() / np.abs(v).max()
+        assert err <= RTOL64, f"plane wave {n},{m1},{m2}: {err:.3e}"
