@@ -12,6 +12,15 @@ using namespace hub;
 
 namespace {
 
+#ifndef HUB_THREADS_51
+#define HUB_THREADS_51 512
+#endif
+constexpr int kThreads51 = HUB_THREADS_51;   // workgroup size of the L = 51 kernels
+#ifndef HUB_HALF_BELOW
+#define HUB_HALF_BELOW 256
+#endif
+constexpr int kHalfBelow = HUB_HALF_BELOW;       // two workgroups per slice below this many slices
+
 thread_local char g_err[512] = "";
 
 hub_status fail(hub_status s, const char* fmt, ...) {
@@ -61,11 +70,14 @@ OpTab<float> op_tab<float>(const hub_ctx* c) {
     return {reinterpret_cast<const cx<float>*>(c->roots32), c->etab32, c->plan, c->L, c->V, c->Nt, c->N};
 }
 
+// Raise a kernel's dynamic-LDS limit once per kernel (and per larger size).
 template <typename K>
 void allow_lds(K kern, size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    static size_t granted = 65536;
+    if (bytes > granted &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)bytes) == hipSuccess)
+        granted = bytes;
 }
 
 // Apply E between a source functor and an epilogue functor over nrhs right-hand sides.
@@ -76,6 +88,21 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Fi
     RedArgs ra{c->partials, c->counters + cid, c->Nt, nrhs};
     if (c->path == HUB_PATH_FUSED) {
         const size_t lds = fused_lds<R>(c);
+        if (c->L == 51 && c->specialized) {
+            if (nrhs * c->Nt < kHalfBelow) {
+                // fewer slices than compute units: two workgroups per slice
+                ra.slots = 2 * c->Nt;
+                auto kern = k_fused_ct<R, 51, kThreads51, true, Src, Epi, Fin>;
+                allow_lds(kern, lds);
+                hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, fin, ra,
+                                   sc, gate);
+                return launch_check("k_fused_ct<51, half>");
+            }
+            auto kern = k_fused_ct<R, 51, kThreads51, false, Src, Epi, Fin>;
+            allow_lds(kern, lds);
+            hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, fin, ra, sc, gate);
+            return launch_check("k_fused_ct<51>");
+        }
         auto kern = k_fused<R, Src, Epi, Fin>;
         allow_lds(kern, lds);
         hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads), lds, st, T, src, epi, fin, ra, sc, gate);
@@ -129,7 +156,7 @@ hub_status apply_M_impl(hub_ctx* c, const R* phi, const void* in, void* out, int
     hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
-    return run_op<R>(c, nrhs, SrcPhasePrev<R>{v, phi}, EpiM<R>{v, static_cast<cx<R>*>(out)}, FinNone{}, 0,
+    return run_op<R>(c, nrhs, SrcPhasePrev<R>{v, PhAngle<R>{phi}}, EpiM<R>{v, static_cast<cx<R>*>(out)}, FinNone{}, 0,
                      static_cast<hipStream_t>(stream), nullptr, GATE_NONE);
 }
 
@@ -138,7 +165,7 @@ hub_status apply_Mdag_impl(hub_ctx* c, const R* phi, const void* in, void* out, 
     hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
-    return run_op<R>(c, nrhs, SrcNext<R>{v}, EpiMdag<R>{v, static_cast<cx<R>*>(out), phi}, FinNone{}, 0,
+    return run_op<R>(c, nrhs, SrcNext<R>{v}, EpiMdag<R>{v, static_cast<cx<R>*>(out), PhAngle<R>{phi}}, FinNone{}, 0,
                      static_cast<hipStream_t>(stream), nullptr, GATE_NONE);
 }
 
@@ -151,7 +178,8 @@ hub_status ensure_cg_workspace(hub_ctx* c) {
     HIP_OR_FAIL(hipMalloc(&c->cg_r, vbytes));
     HIP_OR_FAIL(hipMalloc(&c->cg_p, vbytes));
     HIP_OR_FAIL(hipMalloc(&c->cg_t, vbytes));
-    HIP_OR_FAIL(hipMalloc(&c->phi32, (size_t)c->N * sizeof(float)));
+    HIP_OR_FAIL(hipMalloc(&c->ph64, (size_t)c->N * sizeof(cx<double>)));
+    HIP_OR_FAIL(hipMalloc(&c->ph32, (size_t)c->N * sizeof(cx<float>)));
     HIP_OR_FAIL(hipMalloc(&c->scal, (size_t)c->nrhs_max * sizeof(CgScalars)));
     HIP_OR_FAIL(hipHostMalloc(&c->scal_host, (size_t)c->nrhs_max * sizeof(CgScalars), hipHostMallocDefault));
     c->cg_ready = true;
@@ -162,15 +190,23 @@ hub_status ensure_cg_workspace(hub_ctx* c) {
 template <typename Rlo>
 hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<double>* xhi, int nrhs,
                    const hub_cg_opts& o, hub_cg_info* info, hipStream_t st) {
-    const Rlo* phi_lo;
+    // e^{i phi} once per solve, in FP64 and in the iteration precision
+    cx<double>* ph64 = static_cast<cx<double>*>(c->ph64);
+    hipLaunchKernelGGL(k_phase_table<double>, dim3(1024), dim3(kThreads), 0, st, phi, ph64, c->N);
+    hub_status s0 = launch_check("k_phase_table<double>");
+    if (s0 != HUB_OK) return s0;
+    const cx<Rlo>* ph_lo;
     if constexpr (sizeof(Rlo) == sizeof(float)) {
-        hipLaunchKernelGGL(k_to_float, dim3(1024), dim3(kThreads), 0, st, phi, c->phi32, c->N);
-        hub_status s = launch_check("k_to_float");
-        if (s != HUB_OK) return s;
-        phi_lo = reinterpret_cast<const Rlo*>(c->phi32);
+        hipLaunchKernelGGL(k_phase_table<float>, dim3(1024), dim3(kThreads), 0, st, phi,
+                           static_cast<cx<float>*>(c->ph32), c->N);
+        s0 = launch_check("k_phase_table<float>");
+        if (s0 != HUB_OK) return s0;
+        ph_lo = reinterpret_cast<const cx<Rlo>*>(c->ph32);
     } else {
-        phi_lo = reinterpret_cast<const Rlo*>(phi);
+        ph_lo = reinterpret_cast<const cx<Rlo>*>(ph64);
     }
+    const PhTable<Rlo> tab_lo{ph_lo};
+    const PhTable<double> tab64{ph64};
     cx<double>* rhi = static_cast<cx<double>*>(c->cg_rhi);
     cx<double>* tmp = static_cast<cx<double>*>(c->cg_tmp);
     cx<Rlo>* xlo = static_cast<cx<Rlo>*>(c->cg_x);
@@ -192,10 +228,10 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
                            static_cast<const CgScalars*>(sc));
         hub_status r = launch_check("k_fold_solution");
         if (r != HUB_OK) return r;
-        r = run_op<double>(c, nrhs, SrcNext<double>{xhi}, EpiMdag<double>{xhi, tmp, phi}, FinNone{}, 2, st, sc,
-                           GATE_NOTDONE);
+        r = run_op<double>(c, nrhs, SrcNext<double>{xhi}, EpiMdag<double, PhTable<double>>{xhi, tmp, tab64},
+                           FinNone{}, 2, st, sc, GATE_NOTDONE);
         if (r != HUB_OK) return r;
-        return run_op<double>(c, nrhs, SrcPhasePrev<double>{tmp, phi},
+        return run_op<double>(c, nrhs, SrcPhasePrev<double, PhTable<double>>{tmp, tab64},
                               EpiResidual<Rlo>{tmp, chi, rhi, rlo}, FinResidual{sc}, 3, st, sc, GATE_NOTDONE);
     };
 
@@ -230,11 +266,12 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
         }
         const long long n = std::min<long long>(every, o.max_iter - it);
         for (long long k = 0; k < n; ++k) {
-            s = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p, sc}, EpiSearchMdag<Rlo>{rlo, p, tv, phi_lo, sc},
-                            FinSearch{sc}, 4, st, sc, GATE_ACTIVE);
+            s = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p, sc},
+                            EpiSearchMdag<Rlo, PhTable<Rlo>>{rlo, p, tv, tab_lo, sc}, FinSearch{sc}, 4, st, sc,
+                            GATE_ACTIVE);
             if (s != HUB_OK) return s;
-            s = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo>{tv, phi_lo}, EpiUpdate<Rlo>{tv, p, xlo, rlo, sc},
-                            FinUpdate{sc}, 5, st, sc, GATE_ACTIVE);
+            s = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhTable<Rlo>>{tv, tab_lo},
+                            EpiUpdate<Rlo>{tv, p, xlo, rlo, sc}, FinUpdate{sc}, 5, st, sc, GATE_ACTIVE);
             if (s != HUB_OK) return s;
         }
         it += n;
@@ -323,7 +360,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     CREATE_OR_BAIL(hipMemcpyAsync(c->etab32, etab32.data(), etab32.size() * sizeof(float), hipMemcpyHostToDevice, st));
 
     const SplitGeom G = split_geom(c->L);
-    c->max_partials = std::max(c->Nt, c->Nt * 2 * G.nrb);
+    c->max_partials = std::max(2 * c->Nt, c->Nt * 2 * G.nrb);
     CREATE_OR_BAIL(hipMalloc(&c->partials, (size_t)c->nrhs_max * c->max_partials * sizeof(double)));
     CREATE_OR_BAIL(hipMalloc(&c->counters, kNumCounters * sizeof(unsigned int)));
     CREATE_OR_BAIL(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(unsigned int), st));
@@ -340,8 +377,8 @@ void hub_destroy(hub_ctx* c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
     void* dev[] = {c->roots64, c->roots32, c->etab64, c->etab32, c->partials, c->counters, c->red_out,
-                   c->split_w, c->cg_xhi, c->cg_rhi, c->cg_tmp, c->cg_x, c->cg_r, c->cg_p, c->cg_t,
-                   c->phi32, c->scal, c->force_tmp};
+                   c->split_w, c->cg_rhi, c->cg_tmp, c->cg_x, c->cg_r, c->cg_p, c->cg_t,
+                   c->ph64, c->ph32, c->scal, c->force_tmp};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->scal_host) (void)hipHostFree(c->scal_host);
@@ -388,10 +425,10 @@ hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     const cx<double>* xv = static_cast<const cx<double>*>(x);
     if (nrhs == 1)
-        return run_op<double>(c, 1, SrcNext<double>{xv}, EpiForce{xv, phi, g, 0}, FinNone{}, 0, st, nullptr,
+        return run_op<double>(c, 1, SrcNext<double>{xv}, EpiForce{xv, {phi}, g, 0}, FinNone{}, 0, st, nullptr,
                               GATE_NONE);
     if (!c->force_tmp) HIP_OR_FAIL(hipMalloc(&c->force_tmp, (size_t)c->nrhs_max * c->N * sizeof(double)));
-    s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, phi, c->force_tmp, c->N}, FinNone{}, 0, st,
+    s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, {phi}, c->force_tmp, c->N}, FinNone{}, 0, st,
                        nullptr, GATE_NONE);
     if (s != HUB_OK) return s;
     hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, c->force_tmp, g, c->N, nrhs);

@@ -38,6 +38,9 @@ template <typename R>
 __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
     return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
 }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return fma(a, b, c); }
+
 // a - i b  and  a + i b
 template <typename R>
 __device__ __forceinline__ cx<R> sub_i(cx<R> a, cx<R> b) { return {a.re + b.im, a.im - b.re}; }
@@ -198,6 +201,191 @@ __device__ __forceinline__ void fft_lines(cx<R>* buf, const LineMap lm, int nlin
             fft_dispatch<R, true>(plan.radix[q], buf, lm, nlines, plan.L, plan.len[q], roots);
             __syncthreads();
         }
+    }
+}
+
+}  // namespace hub
+
+// ============================================================================ compile-time L
+// The same transform with L known at compile time: the radix plan, every index
+// division and the r-point DFT coefficients become constants.
+namespace hub {
+
+struct CPlan {
+    int nst;
+    int radix[kMaxStages];
+    int len[kMaxStages];
+};
+
+constexpr CPlan make_cplan(int L) {
+    CPlan p{};
+    const int rads[] = {4, 2, 3, 5, 7, 11, 13, 17};
+    int rest = L;
+    for (int r : rads)
+        while (rest % r == 0 && p.nst < kMaxStages) {
+            p.radix[p.nst++] = r;
+            rest /= r;
+        }
+    int len = L;
+    for (int q = 0; q < p.nst; ++q) {
+        p.len[q] = len;
+        len /= p.radix[q];
+    }
+    return p;
+}
+
+// cos and sin of pi/4 * a, 0 <= a <= 1, by Taylor series (compile time only)
+constexpr void ct_sincos_octant(double a, double* s, double* c) {
+    const double x = 0.78539816339744830962 * a;
+    const double z = x * x;
+    double ts = x, tc = 1.0, ss = x, cs = 1.0;
+    for (int n = 1; n < 14; ++n) {
+        ts *= -z / ((2.0 * n) * (2.0 * n + 1.0));
+        tc *= -z / ((2.0 * n - 1.0) * (2.0 * n));
+        ss += ts;
+        cs += tc;
+    }
+    *s = ss;
+    *c = cs;
+}
+
+// cos(2 pi m / r) and sin(2 pi m / r) by octant reduction with integer arithmetic.
+constexpr void ct_sincos_frac(int m, int r, double* s, double* c) {
+    m %= r;
+    if (m < 0) m += r;
+    const int o = (8 * m) / r;
+    const int rem = 8 * m - o * r;
+    double sa = 0, ca = 0, sb = 0, cb = 0;
+    ct_sincos_octant((double)rem / r, &sa, &ca);            // a = (pi/4) rem/r
+    ct_sincos_octant((double)(r - rem) / r, &sb, &cb);      // b = pi/4 - a
+    switch (o) {
+        case 0: *c = ca;  *s = sa;  break;
+        case 1: *c = sb;  *s = cb;  break;
+        case 2: *c = -sa; *s = ca;  break;
+        case 3: *c = -cb; *s = sb;  break;
+        case 4: *c = -ca; *s = -sa; break;
+        case 5: *c = -sb; *s = -cb; break;
+        case 6: *c = sa;  *s = -ca; break;
+        default: *c = cb; *s = -sb; break;
+    }
+}
+
+template <int RAD>
+struct DftConst {
+    double c[RAD];
+    double s[RAD];
+    constexpr DftConst() : c(), s() {
+        for (int m = 0; m < RAD; ++m) ct_sincos_frac(m, RAD, &s[m], &c[m]);
+    }
+};
+
+// r-point DFT with constant coefficients (same arithmetic as small_dft).
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void small_dft_ct(cx<R>* x) {
+    if constexpr (RAD <= 4) {
+        small_dft<R, RAD, INV>(x, nullptr, nullptr);
+    } else {
+        constexpr DftConst<RAD> K{};
+        constexpr int H = (RAD - 1) / 2;
+        cx<R> e[H + 1], o[H + 1];
+        const cx<R> x0 = x[0];
+        cx<R> s0 = x0;
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            e[j] = x[j] + x[RAD - j];
+            o[j] = x[j] - x[RAD - j];
+            s0 = s0 + e[j];
+        }
+        x[0] = s0;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            cx<R> A = x0;
+            cx<R> B = {(R)0, (R)0};
+#pragma unroll
+            for (int j = 1; j <= H; ++j) {
+                const int m = (j * k) % RAD;
+                const R cm = (R)K.c[m], sm = (R)K.s[m];
+                A.re = fmar(cm, e[j].re, A.re);
+                A.im = fmar(cm, e[j].im, A.im);
+                B.re = fmar(sm, o[j].re, B.re);
+                B.im = fmar(sm, o[j].im, B.im);
+            }
+            if constexpr (!INV) {
+                x[k] = sub_i(A, B);
+                x[RAD - k] = add_i(A, B);
+            } else {
+                x[k] = add_i(A, B);
+                x[RAD - k] = sub_i(A, B);
+            }
+        }
+    }
+}
+
+// Stage Q of the row (COLS = false) or column (COLS = true) transforms of NS
+// sublattice tiles [NS][L][L] in LDS (a whole slice when NS = 2).  Row tasks run along a line (consecutive threads read
+// consecutive positions); column tasks run across lines (consecutive threads read
+// consecutive columns), so neither direction has strided LDS access within a wave.
+template <typename R, int L, int Q, bool INV, bool COLS, int NT, int NS = 2>
+__device__ __forceinline__ void ct_stage(cx<R>* __restrict__ buf, const cx<R>* __restrict__ roots) {
+    constexpr CPlan P = make_cplan(L);
+    constexpr int RAD = P.radix[Q], LQ = P.len[Q], M = LQ / RAD, PER = L / RAD;
+    constexpr int NL = NS * L, NTASK = NL * PER, TWS = L / LQ;
+    constexpr int ST = COLS ? M * L : M;
+    for (int task = threadIdx.x; task < NTASK; task += NT) {
+        int line, j;
+        if constexpr (COLS) {
+            j = task / NL;
+            line = task - j * NL;
+        } else {
+            line = task / PER;
+            j = task - line * PER;
+        }
+        const int b = j / M, np = j - b * M;
+        int base;
+        if constexpr (COLS) {
+            const int s = line >= L ? 1 : 0;
+            base = s * L * L + (line - s * L) + (b * LQ + np) * L;
+        } else {
+            base = line * L + b * LQ + np;
+        }
+        cx<R> x[RAD];
+#pragma unroll
+        for (int i = 0; i < RAD; ++i) x[i] = buf[base + i * ST];
+        if constexpr (!INV) {
+            small_dft_ct<R, RAD, false>(x);
+            if constexpr (M > 1) {
+#pragma unroll
+                for (int k = 1; k < RAD; ++k) x[k] = cmul(x[k], roots[np * k * TWS]);
+            }
+        } else {
+            if constexpr (M > 1) {
+#pragma unroll
+                for (int k = 1; k < RAD; ++k) x[k] = cmulc(x[k], roots[np * k * TWS]);
+            }
+            small_dft_ct<R, RAD, true>(x);
+        }
+#pragma unroll
+        for (int i = 0; i < RAD; ++i) buf[base + i * ST] = x[i];
+    }
+}
+
+// Forward stages Q..QEND-1 (each followed by a barrier).
+template <typename R, int L, int Q, int QEND, bool COLS, int NT, int NS = 2>
+__device__ __forceinline__ void ct_forward(cx<R>* buf, const cx<R>* roots) {
+    if constexpr (Q < QEND) {
+        ct_stage<R, L, Q, false, COLS, NT, NS>(buf, roots);
+        __syncthreads();
+        ct_forward<R, L, Q + 1, QEND, COLS, NT, NS>(buf, roots);
+    }
+}
+
+// Inverse stages Q, Q-1, ..., QLO (each followed by a barrier).
+template <typename R, int L, int Q, int QLO, bool COLS, int NT, int NS = 2>
+__device__ __forceinline__ void ct_inverse(cx<R>* buf, const cx<R>* roots) {
+    if constexpr (Q >= QLO) {
+        ct_stage<R, L, Q, true, COLS, NT, NS>(buf, roots);
+        __syncthreads();
+        ct_inverse<R, L, Q - 1, QLO, COLS, NT, NS>(buf, roots);
     }
 }
 

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hub.h"
+#include "hub.h"
 
 namespace hub {
 
@@ -62,6 +62,7 @@ struct hub_ctx {
     long long N = 0;                 // V * Nt
     double beta = 0, kappa = 0, delta = 0;
     int path = HUB_PATH_FUSED;
+    bool specialized = true;         // use a compile-time-L kernel when one exists
     int lds_fused64 = 0, lds_fused32 = 0;
     int max_lds = 0;
     hub::FftPlan plan{};
@@ -83,14 +84,14 @@ struct hub_ctx {
 
     // CG workspace (allocated on first solve)
     bool cg_ready = false;
-    void* cg_xhi = nullptr;      // complex128 (when use_x0 == 0 the user's x is used directly)
     void* cg_rhi = nullptr;      // complex128
     void* cg_tmp = nullptr;      // complex128 (M^dag x_hi)
     void* cg_x = nullptr;        // complex128 (FP64 mode) or complex64 (mixed)
     void* cg_r = nullptr;
     void* cg_p = nullptr;
     void* cg_t = nullptr;
-    float* phi32 = nullptr;      // [Nt][V]
+    void* ph64 = nullptr;        // e^{i phi} complex128 [Nt][V] for the solve in progress
+    void* ph32 = nullptr;        // e^{i phi} complex64 [Nt][V]
     hub::CgScalars* scal = nullptr;      // device [nrhs_max]
     hub::CgScalars* scal_host = nullptr; // pinned host mirror
     double* force_tmp = nullptr;         // [nrhs_max][N] doubles, per-rhs force before summation

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "hub_fft.hpp"
+#include "hub_math.hpp"
 
 namespace hub {
 
@@ -88,123 +89,186 @@ __device__ __forceinline__ bool gate_open(const CgScalars* sc, int gate, int rhs
     return sc[rhs].done == 0;
 }
 
-// ----------------------------------------------------------------------------- phases
-__device__ __forceinline__ void sincos_r(double a, double* s, double* c) { sincos(a, s, c); }
-__device__ __forceinline__ void sincos_r(float a, float* s, float* c) { sincosf(a, s, c); }
-
-template <typename R>
-__device__ __forceinline__ cx<R> phase(const R* phi, long long idx) {
-    R s, c;
-    sincos_r(phi[idx], &s, &c);
-    return {c, s};
-}
-
 __device__ __forceinline__ int prev_slice(int t, int Nt) { return t == 0 ? Nt - 1 : t - 1; }
 __device__ __forceinline__ int next_slice(int t, int Nt) { return t == Nt - 1 ? 0 : t + 1; }
 
-// ----------------------------------------------------------------------------- sources
-// A source functor names the slice that feeds destination slice t and loads its
-// entries (before E acts).
+// ----------------------------------------------------------------------------- phases
+// Where the phases e^{i phi} come from: the angles themselves (evaluated per use), or
+// a table of e^{i phi} computed once (the solver computes one per solve).
 template <typename R>
-struct SrcPhasePrev {            // e^{i phi_{t-1}} v_{t-1}            (M)
-    const cx<R>* v;
+struct PhAngle {
+    using Pre = R;
     const R* phi;
+    __device__ Pre fetch(long long k) const { return phi[k]; }
+    __device__ cx<R> value(Pre a) const {
+        R s, c;
+        phase_sincos(a, &s, &c);
+        return {c, s};
+    }
+};
+
+template <typename R>
+struct PhTable {
+    using Pre = cx<R>;
+    const cx<R>* tab;
+    __device__ Pre fetch(long long k) const { return tab[k]; }
+    __device__ cx<R> value(Pre a) const { return a; }
+};
+
+// ----------------------------------------------------------------------------- sources
+// A source functor names the slice that feeds destination slice t and produces its
+// entries (before E acts) in two steps: fetch() issues the global loads into a
+// per-entry record, make() turns the record into the complex entry.  Kernels that
+// know their trip counts issue every fetch before the first make.
+template <typename R, class Ph>
+struct PrePh {
+    cx<R> v;
+    typename Ph::Pre ph;
+};
+
+template <typename R, class Ph = PhAngle<R>>
+struct SrcPhasePrev {            // e^{i phi_{t-1}} v_{t-1}            (M)
+    using Pre = PrePh<R, Ph>;
+    const cx<R>* v;
+    Ph ph;
     __device__ int slice(int t, int Nt) const { return prev_slice(t, Nt); }
-    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+    __device__ Pre fetch(int rhs, int ts, int i, const OpTab<R>& T) const {
         const long long k = (long long)ts * T.V + i;
-        return cmul(v[rhs * T.N + k], phase(phi, k));
+        return {v[rhs * T.N + k], ph.fetch(k)};
+    }
+    __device__ cx<R> make(const Pre& a, int) const { return cmul(a.v, ph.value(a.ph)); }
+    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+        return make(fetch(rhs, ts, i, T), rhs);
     }
 };
 
 template <typename R>
 struct SrcNext {                 // v_{t+1}                            (M^dag, force)
+    using Pre = cx<R>;
     const cx<R>* v;
     __device__ int slice(int t, int Nt) const { return next_slice(t, Nt); }
-    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+    __device__ Pre fetch(int rhs, int ts, int i, const OpTab<R>& T) const {
         return v[rhs * T.N + (long long)ts * T.V + i];
     }
+    __device__ cx<R> make(const Pre& a, int) const { return a; }
+    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+        return make(fetch(rhs, ts, i, T), rhs);
+    }
+};
+
+template <typename R>
+struct PrePair {
+    cx<R> a, b;
 };
 
 template <typename R>
 struct SrcSearchNext {           // (r + beta p)_{t+1}                 (CG: M^dag of the new direction)
+    using Pre = PrePair<R>;
     const cx<R>* r;
     const cx<R>* p;
     const CgScalars* sc;
     __device__ int slice(int t, int Nt) const { return next_slice(t, Nt); }
-    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+    __device__ Pre fetch(int rhs, int ts, int i, const OpTab<R>& T) const {
         const long long k = rhs * T.N + (long long)ts * T.V + i;
+        return {r[k], p[k]};
+    }
+    __device__ cx<R> make(const Pre& a, int rhs) const {
         const R b = (R)sc[rhs].beta;
-        const cx<R> rv = r[k], pv = p[k];
-        return {rv.re + b * pv.re, rv.im + b * pv.im};
+        return {a.a.re + b * a.b.re, a.a.im + b * a.b.im};
+    }
+    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
+        return make(fetch(rhs, ts, i, T), rhs);
     }
 };
 
 // ----------------------------------------------------------------------------- epilogues
-// An epilogue functor receives w = (E src)_{t,i} for destination slice t and site i,
-// writes its outputs and adds its contribution to the block's reduction.
+// An epilogue functor receives w = (E src)_{t,i} for destination slice t and site i.
+// fetch() issues the loads the epilogue needs, store() writes its outputs and adds its
+// contribution to the block's reduction.
 template <typename R>
 struct EpiM {                    // out_t = v_t - B_t w
+    using Pre = cx<R>;
     const cx<R>* v;
     cx<R>* out;
-    __device__ void operator()(int rhs, int t, int i, cx<R> w, const OpTab<R>& T, double&) const {
-        const long long k = rhs * T.N + (long long)t * T.V + i;
-        const cx<R> a = v[k];
-        out[k] = (t == 0) ? a + w : a - w;
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
+        return v[rhs * T.N + (long long)t * T.V + i];
+    }
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, double&) const {
+        out[rhs * T.N + (long long)t * T.V + i] = (t == 0) ? a + w : a - w;
     }
 };
 
-template <typename R>
+template <typename R, class Ph = PhAngle<R>>
 struct EpiMdag {                 // out_t = v_t - B_{t+1} e^{-i phi_t} w
+    using Pre = PrePh<R, Ph>;
     const cx<R>* v;
     cx<R>* out;
-    const R* phi;
-    __device__ void operator()(int rhs, int t, int i, cx<R> w, const OpTab<R>& T, double&) const {
+    Ph ph;
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
         const long long ks = (long long)t * T.V + i;
-        const long long k = rhs * T.N + ks;
-        const cx<R> pw = cmulc(w, phase(phi, ks));
-        const cx<R> a = v[k];
-        out[k] = (t == T.Nt - 1) ? a + pw : a - pw;
+        return {v[rhs * T.N + ks], ph.fetch(ks)};
+    }
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, double&) const {
+        const cx<R> pw = cmulc(w, ph.value(a.ph));
+        out[rhs * T.N + (long long)t * T.V + i] = (t == T.Nt - 1) ? a.v + pw : a.v - pw;
     }
 };
 
-template <typename R>
+template <typename R, class Ph>
+struct PreSearch {
+    cx<R> r, p;
+    typename Ph::Pre ph;
+};
+
+template <typename R, class Ph = PhAngle<R>>
 struct EpiSearchMdag {           // CG: tv_t = (r + beta p)_t - B_{t+1} e^{-i phi_t} w ; acc |tv|^2
+    using Pre = PreSearch<R, Ph>;
     const cx<R>* r;
     const cx<R>* p;
     cx<R>* tv;
-    const R* phi;
+    Ph ph;
     const CgScalars* sc;
-    __device__ void operator()(int rhs, int t, int i, cx<R> w, const OpTab<R>& T, double& acc) const {
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
         const long long ks = (long long)t * T.V + i;
         const long long k = rhs * T.N + ks;
+        return {r[k], p[k], ph.fetch(ks)};
+    }
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, double& acc) const {
         const R b = (R)sc[rhs].beta;
-        const cx<R> rv = r[k], pv = p[k];
-        const cx<R> pn = {rv.re + b * pv.re, rv.im + b * pv.im};
-        const cx<R> pw = cmulc(w, phase(phi, ks));
+        const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
+        const cx<R> pw = cmulc(w, ph.value(a.ph));
         const cx<R> o = (t == T.Nt - 1) ? pn + pw : pn - pw;
-        tv[k] = o;
+        tv[rhs * T.N + (long long)t * T.V + i] = o;
         acc += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
     }
 };
 
 template <typename R>
+struct PreUpdate {
+    cx<R> tq, p, x, r;
+};
+
+template <typename R>
 struct EpiUpdate {               // CG: q = tv_t - B_t w; p = r + beta p; x += alpha p; r -= alpha q; acc |r|^2
+    using Pre = PreUpdate<R>;
     const cx<R>* tv;
     cx<R>* p;
     cx<R>* x;
     cx<R>* r;
     const CgScalars* sc;
-    __device__ void operator()(int rhs, int t, int i, cx<R> w, const OpTab<R>& T, double& acc) const {
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
+        const long long k = rhs * T.N + (long long)t * T.V + i;
+        return {tv[k], p[k], x[k], r[k]};
+    }
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, double& acc) const {
         const long long k = rhs * T.N + (long long)t * T.V + i;
         const R b = (R)sc[rhs].beta;
-        const R a = (R)sc[rhs].alpha;
-        const cx<R> tq = tv[k];
-        const cx<R> q = (t == 0) ? tq + w : tq - w;
-        const cx<R> rv = r[k], pv = p[k], xv = x[k];
-        const cx<R> pn = {rv.re + b * pv.re, rv.im + b * pv.im};
-        const cx<R> rn = {rv.re - a * q.re, rv.im - a * q.im};
+        const R al = (R)sc[rhs].alpha;
+        const cx<R> q = (t == 0) ? a.tq + w : a.tq - w;
+        const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
+        const cx<R> rn = {a.r.re - al * q.re, a.r.im - al * q.im};
         p[k] = pn;
-        x[k] = {xv.re + a * pn.re, xv.im + a * pn.im};
+        x[k] = {a.x.re + al * pn.re, a.x.im + al * pn.im};
         r[k] = rn;
         acc += (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
     }
@@ -212,15 +276,20 @@ struct EpiUpdate {               // CG: q = tv_t - B_t w; p = r + beta p; x += a
 
 template <typename Rlo>
 struct EpiResidual {             // FP64: r_hi = chi - (y_t - B_t w) with y = M^dag x_hi; r_lo = r_hi; acc |r_hi|^2
+    using Pre = PrePair<double>;
     const cx<double>* y;
     const cx<double>* chi;
     cx<double>* rhi;
     cx<Rlo>* rlo;
-    __device__ void operator()(int rhs, int t, int i, cx<double> w, const OpTab<double>& T, double& acc) const {
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<double>& T) const {
         const long long k = rhs * T.N + (long long)t * T.V + i;
-        const cx<double> yv = y[k];
-        const cx<double> q = (t == 0) ? yv + w : yv - w;
-        const cx<double> rv = chi[k] - q;
+        return {y[k], chi[k]};
+    }
+    __device__ void store(int rhs, int t, int i, cx<double> w, const Pre& a, const OpTab<double>& T,
+                          double& acc) const {
+        const long long k = rhs * T.N + (long long)t * T.V + i;
+        const cx<double> q = (t == 0) ? a.a + w : a.a - w;
+        const cx<double> rv = a.b - q;
         rhi[k] = rv;
         rlo[k] = {(Rlo)rv.re, (Rlo)rv.im};
         acc += rv.re * rv.re + rv.im * rv.im;
@@ -228,17 +297,30 @@ struct EpiResidual {             // FP64: r_hi = chi - (y_t - B_t w) with y = M^
 };
 
 struct EpiForce {                // g_t = -2 B_{t+1} Im(e^{i phi_t} x_t conj(w)),  w = (E x_{t+1})
+    using Pre = PrePh<double, PhAngle<double>>;
     const cx<double>* x;
-    const double* phi;
+    PhAngle<double> ph;
     double* g;                   // [nrhs or 1][Nt][V]
     long long g_rhs_stride;      // 0 when there is one right-hand side
-    __device__ void operator()(int rhs, int t, int i, cx<double> w, const OpTab<double>& T, double&) const {
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<double>& T) const {
         const long long ks = (long long)t * T.V + i;
-        const cx<double> z = cmulc(cmul(x[rhs * T.N + ks], phase(phi, ks)), w);
+        return {x[rhs * T.N + ks], ph.fetch(ks)};
+    }
+    __device__ void store(int rhs, int t, int i, cx<double> w, const Pre& a, const OpTab<double>& T,
+                          double&) const {
+        const long long ks = (long long)t * T.V + i;
+        const cx<double> z = cmulc(cmul(a.v, ph.value(a.ph)), w);
         const double bn = (t == T.Nt - 1) ? -1.0 : 1.0;
         g[rhs * g_rhs_stride + ks] = -2.0 * bn * z.im;
     }
 };
+
+// fetch + store in one call (kernels that do not prefetch)
+template <typename R, class Epi>
+__device__ __forceinline__ void epi_apply(const Epi& epi, int rhs, int t, int i, cx<R> w, const OpTab<R>& T,
+                                          double& acc) {
+    epi.store(rhs, t, i, w, epi.fetch(rhs, t, i, T), T, acc);
+}
 
 // ----------------------------------------------------------------------------- finalizers
 struct FinNone {
@@ -381,9 +463,166 @@ k_fused(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const Red
         __syncthreads();
         fft_lines<R, true>(buf, cols, 2 * L, T.plan, roots);
         fft_lines<R, true>(buf, rows, 2 * L, T.plan, roots);
-        for (int i = threadIdx.x; i < V; i += blockDim.x) epi(rhs, t, i, buf[i], T, acc);
+        for (int i = threadIdx.x; i < V; i += blockDim.x) epi_apply(epi, rhs, t, i, buf[i], T, acc);
     }
     if constexpr (Fin::kReduce) reduce_and_finalize(acc, rhs, t, ra, fin, red_lds);
+}
+
+// Same layout with L known at compile time (NT threads per workgroup).  The first
+// row stage is fused into the source load and the last inverse row stage into the
+// epilogue, so the slice makes two fewer round trips through LDS.  Every global load
+// is issued early: all source entries and E(k) values before the first butterfly, the
+// epilogue operands one stage before they are needed; each thread keeps them in
+// registers.
+//
+// HALF = true runs two workgroups per slice when there are fewer slices than compute
+// units: both transform the whole source slice forward (the 2 x 2 hopping exponential
+// couples the sublattices), and each mixes, transforms back and writes one sublattice.
+// Three quarters of the arithmetic per workgroup, no communication between them.
+template <int BYTES>
+struct EpiPrefetchFits {
+    static constexpr bool value = BYTES <= 400;   // register budget per thread
+};
+
+template <typename R, int L, int NT, bool HALF, class Src, class Epi, class Fin>
+__global__ void __launch_bounds__(NT)
+k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const RedArgs ra,
+           const CgScalars* sc, int gate) {
+    constexpr CPlan P = make_cplan(L);
+    static_assert(P.nst >= 1, "L = 1 takes the generic kernel");
+    constexpr int LL = L * L, V = 2 * LL;
+    constexpr int R0 = P.radix[0], M0 = L / R0;
+    constexpr int NT0 = 2 * L * M0;                     // stage-0 tasks over both sublattices
+    constexpr int NTE = HALF ? L * M0 : NT0;            // stage-0 tasks of the sublattices written
+    constexpr int ROUNDS0 = (NT0 + NT - 1) / NT;
+    constexpr int ROUNDSO = (NTE + NT - 1) / NT;
+    constexpr int ROUNDSE = (LL + NT - 1) / NT;         // momenta per thread in the mix
+    constexpr bool kPreEpi = EpiPrefetchFits<(int)sizeof(typename Epi::Pre) * ROUNDSO * R0>::value;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    cx<R>* roots = buf + V;
+    const int u = xcd_linear(blockIdx.x, gridDim.x);
+    const int q = HALF ? (u >> 1) : u;
+    const int h = HALF ? (u & 1) : 0;                   // sublattice written (HALF only)
+    const int rhs = q / T.Nt, t = q - rhs * T.Nt;
+    const int off = HALF ? h * LL : 0;                  // first site written
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    if (gate_open(sc, gate, rhs)) {
+        const int ts = src.slice(t, T.Nt);
+        // issue every global load of the source and of E(k)
+        typename Src::Pre pre[ROUNDS0][R0];
+#pragma unroll
+        for (int rd = 0; rd < ROUNDS0; ++rd) {
+            const int task = tid + rd * NT;
+            if (task < NT0) {
+                const int line = task / M0, np = task - line * M0;
+#pragma unroll
+                for (int i = 0; i < R0; ++i) pre[rd][i] = src.fetch(rhs, ts, line * L + np + i * M0, T);
+            }
+        }
+        R ec[ROUNDSE][3];
+#pragma unroll
+        for (int rd = 0; rd < ROUNDSE; ++rd) {
+            const int p = tid + rd * NT;
+            if (p < LL) {
+                ec[rd][0] = T.etab[4 * p];
+                ec[rd][1] = T.etab[4 * p + 1];
+                ec[rd][2] = T.etab[4 * p + 2];
+            }
+        }
+        for (int i = tid; i < L; i += NT) roots[i] = T.roots[i];
+        __syncthreads();
+        // row stage 0 (natural-order input) from the prefetched entries
+#pragma unroll
+        for (int rd = 0; rd < ROUNDS0; ++rd) {
+            const int task = tid + rd * NT;
+            if (task < NT0) {
+                const int line = task / M0, np = task - line * M0;
+                const int base = line * L + np;
+                cx<R> x[R0];
+#pragma unroll
+                for (int i = 0; i < R0; ++i) x[i] = src.make(pre[rd][i], rhs);
+                small_dft_ct<R, R0, false>(x);
+                if constexpr (M0 > 1) {
+#pragma unroll
+                    for (int k = 1; k < R0; ++k) x[k] = cmul(x[k], roots[np * k]);
+                }
+#pragma unroll
+                for (int i = 0; i < R0; ++i) buf[base + i * M0] = x[i];
+            }
+        }
+        __syncthreads();
+        ct_forward<R, L, 1, P.nst, false, NT>(buf, roots);
+        ct_forward<R, L, 0, P.nst, true, NT>(buf, roots);
+        // E(k): A' = c A + sf B,  B' = conj(sf) A + c B
+#pragma unroll
+        for (int rd = 0; rd < ROUNDSE; ++rd) {
+            const int p = tid + rd * NT;
+            if (p < LL) {
+                const R c = ec[rd][0], sr = ec[rd][1], si = ec[rd][2];
+                const cx<R> a = buf[p], b = buf[LL + p];
+                const cx<R> na = {c * a.re + sr * b.re - si * b.im, c * a.im + sr * b.im + si * b.re};
+                const cx<R> nb = {c * b.re + sr * a.re + si * a.im, c * b.im + sr * a.im - si * a.re};
+                if (!HALF || h == 0) buf[p] = na;
+                if (!HALF || h == 1) buf[LL + p] = nb;
+            }
+        }
+        __syncthreads();
+        constexpr int NS = HALF ? 1 : 2;
+        cx<R>* own = buf + off;
+        ct_inverse<R, L, P.nst - 1, 0, true, NT, NS>(own, roots);
+        // epilogue operands, issued while the last inverse row stages run
+        typename Epi::Pre ep[kPreEpi ? ROUNDSO : 1][kPreEpi ? R0 : 1];
+        if constexpr (kPreEpi) {
+#pragma unroll
+            for (int rd = 0; rd < ROUNDSO; ++rd) {
+                const int task = tid + rd * NT;
+                if (task < NTE) {
+                    const int line = task / M0, np = task - line * M0;
+#pragma unroll
+                    for (int i = 0; i < R0; ++i) ep[rd][i] = epi.fetch(rhs, t, off + line * L + np + i * M0, T);
+                }
+            }
+        }
+        ct_inverse<R, L, P.nst - 1, 1, false, NT, NS>(own, roots);
+        // row stage 0 inverse (natural-order output) straight into the epilogue
+#pragma unroll
+        for (int rd = 0; rd < ROUNDSO; ++rd) {
+            const int task = tid + rd * NT;
+            if (task < NTE) {
+                const int line = task / M0, np = task - line * M0;
+                const int base = line * L + np;
+                cx<R> x[R0];
+#pragma unroll
+                for (int k = 0; k < R0; ++k) x[k] = own[base + k * M0];
+                if constexpr (M0 > 1) {
+#pragma unroll
+                    for (int k = 1; k < R0; ++k) x[k] = cmulc(x[k], roots[np * k]);
+                }
+                small_dft_ct<R, R0, true>(x);
+#pragma unroll
+                for (int i = 0; i < R0; ++i) {
+                    if constexpr (kPreEpi) epi.store(rhs, t, off + base + i * M0, x[i], ep[rd][i], T, acc);
+                    else epi_apply(epi, rhs, t, off + base + i * M0, x[i], T, acc);
+                }
+            }
+        }
+    }
+    if constexpr (Fin::kReduce) reduce_and_finalize(acc, rhs, HALF ? 2 * t + h : t, ra, fin, red_lds);
+}
+
+// e^{i phi} as a table, evaluated in FP64 and rounded once to R
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+k_phase_table(const double* __restrict__ phi, cx<R>* __restrict__ tab, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double s, c;
+        phase_sincos(phi[i], &s, &c);
+        tab[i] = {(R)c, (R)s};
+    }
 }
 
 // ----------------------------------------------------------------------------- split kernels
@@ -487,7 +726,7 @@ k_split_rows_inv(const OpTab<R> T, const SplitGeom G, const cx<R>* __restrict__ 
         for (int i = threadIdx.x; i < nr * L; i += blockDim.x) buf[i] = srcp[i];
         __syncthreads();
         fft_lines<R, true>(buf, LineMap{1, L, 0, 1}, nr, T.plan, roots);
-        for (int i = threadIdx.x; i < nr * L; i += blockDim.x) epi(rhs, t, off + i, buf[i], T, acc);
+        for (int i = threadIdx.x; i < nr * L; i += blockDim.x) epi_apply(epi, rhs, t, off + i, buf[i], T, acc);
     }
     if constexpr (Fin::kReduce) reduce_and_finalize(acc, rhs, slot, ra, fin, red_lds);
 }

@@ -158,3 +158,30 @@ def test_free_plane_waves_at_scale(w):
         # M v is a difference of two terms of size |v|
         err = np.abs(got - lam * v).max() / np.abs(v).max()
         assert err <= RTOL64, f"plane wave {n},{m1},{m2}: {err:.3e}"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_half_and_whole_slice_kernels_agree(prec):
+    """L = 51: one right-hand side runs two workgroups per slice (each writes one
+    sublattice), two right-hand sides run one workgroup per slice; both match the oracle."""
+    w = PREC
+    print(f"[case] paired vs single {prec} {w.name}", flush=True)
+    phi, v = draw_inputs(w, seed=18, nrhs=2)
+    hub = _hub(w, nrhs=2)
+    op = oracle_op(w, mode="expm")
+    if prec == "fp64":
+        P, V = to_dev(phi), to_dev(v)
+        one = [to_np(hub.apply_M(P, V[r:r + 1].contiguous())) for r in range(2)]
+        two = to_np(hub.apply_M(P, V))
+        ref = op.apply_M(phi, v)
+        tol = RTOL64
+    else:
+        p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
+        P, V = to_dev(p32), to_dev(v32)
+        one = [to_np(hub.apply_M_c64(P, V[r:r + 1].contiguous())) for r in range(2)]
+        two = to_np(hub.apply_M_c64(P, V))
+        ref = op.apply_M(p32.astype(np.float64), v32.astype(np.complex128))
+        tol = RTOL32
+    for r in range(2):
+        assert_close_elementwise(one[r][0], ref[r], tol, f"half-slice kernel rhs {r}")
+        assert_close_elementwise(two[r], ref[r], tol, f"whole-slice kernel rhs {r}")
