@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 
 #include "hub_kernels.hpp"
 
@@ -70,14 +72,18 @@ OpTab<float> op_tab<float>(const hub_ctx* c) {
     return {reinterpret_cast<const cx<float>*>(c->roots32), c->etab32, c->plan, c->L, c->V, c->Nt, c->N};
 }
 
-// Raise a kernel's dynamic-LDS limit once per kernel (and per larger size).
+// Raise a kernel's dynamic-LDS limit once per kernel (and again for a larger size).
 template <typename K>
 void allow_lds(K kern, size_t bytes) {
-    static size_t granted = 65536;
-    if (bytes > granted &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)bytes) == hipSuccess)
-        granted = bytes;
+    static std::mutex mu;
+    static std::unordered_map<const void*, size_t> granted;
+    if (bytes <= 65536) return;
+    const void* key = reinterpret_cast<const void*>(kern);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = granted.find(key);
+    if (it != granted.end() && it->second >= bytes) return;
+    if (hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        granted[key] = bytes;
 }
 
 // Apply E between a source functor and an epilogue functor over nrhs right-hand sides.
@@ -224,7 +230,7 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     if (s != HUB_OK) return s;
 
     auto reliable_update = [&]() -> hub_status {
-        hipLaunchKernelGGL(k_fold_solution<Rlo>, dim3(blocks), dim3(kThreads), 0, st, xhi, xlo, c->V, c->Nt,
+        hipLaunchKernelGGL(k_fold_solution<Rlo>, dim3(512, nrhs), dim3(kThreads), 0, st, xhi, xlo, c->N,
                            static_cast<const CgScalars*>(sc));
         hub_status r = launch_check("k_fold_solution");
         if (r != HUB_OK) return r;

@@ -53,6 +53,11 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 // Store this block's partial, and let the block that arrives last sum every right-hand
 // side's partials in slot order and call fin(rhs, sum).  Deterministic: the final sums
 // never depend on arrival order.  `lds` needs 64 doubles.
+//
+// The partials and the arrival counter are device-scope relaxed atomics (coherent
+// across XCDs without writing back or invalidating the L2s); the partial's store is
+// complete (s_waitcnt) before the counter increment is issued, so the block that sees
+// the final count reads every partial.
 template <class Fin>
 __device__ __forceinline__ void reduce_and_finalize(double acc, int rhs, int slot, const RedArgs& ra,
                                                     const Fin& fin, double* lds) {
@@ -61,13 +66,14 @@ __device__ __forceinline__ void reduce_and_finalize(double acc, int rhs, int slo
     if (threadIdx.x == 0) {
         __hip_atomic_store(&ra.partials[(long long)rhs * ra.slots + slot], s, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(ra.counter, 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const unsigned prev = __hip_atomic_fetch_add(ra.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         is_last = (prev == gridDim.x * gridDim.y * gridDim.z - 1) ? 1 : 0;
     }
     __syncthreads();
     if (!is_last) return;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
     for (int r = 0; r < ra.nrhs; ++r) {
         double v = 0.0;
         for (int j = threadIdx.x; j < ra.slots; j += blockDim.x)
@@ -757,19 +763,20 @@ k_cg_init(const cx<double>* __restrict__ chi, cx<double>* __restrict__ xhi, cx<d
     reduce_and_finalize(acc, rhs, t, ra, fin, red_lds);
 }
 
+// x_hi += x_lo, x_lo = 0 for right-hand sides not yet done (grid-stride over N per rhs,
+// gridDim.y = nrhs)
 template <typename Rlo>
 __global__ void __launch_bounds__(kThreads)
-k_fold_solution(cx<double>* __restrict__ xhi, cx<Rlo>* __restrict__ xlo, int V, int Nt,
-                const CgScalars* sc) {
-    const int t = blockIdx.x % Nt, rhs = blockIdx.x / Nt;
+k_fold_solution(cx<double>* __restrict__ xhi, cx<Rlo>* __restrict__ xlo, long long N, const CgScalars* sc) {
+    const int rhs = blockIdx.y;
     if (sc[rhs].done) return;
-    const long long base = (long long)rhs * V * Nt + (long long)t * V;
-    for (int i = threadIdx.x; i < V; i += blockDim.x) {
-        const long long k = base + i;
-        const cx<Rlo> a = xlo[k];
-        const cx<double> h = xhi[k];
-        xhi[k] = {h.re + (double)a.re, h.im + (double)a.im};
-        xlo[k] = {(Rlo)0, (Rlo)0};
+    const long long base = (long long)rhs * N;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const cx<Rlo> a = xlo[base + i];
+        const cx<double> h = xhi[base + i];
+        xhi[base + i] = {h.re + (double)a.re, h.im + (double)a.im};
+        xlo[base + i] = {(Rlo)0, (Rlo)0};
     }
 }
 
