@@ -86,54 +86,72 @@ void allow_lds(K kern, size_t bytes) {
         granted[key] = bytes;
 }
 
+// Which operator kernel runs for nrhs right-hand sides, and how many reduction slots
+// (blocks per right-hand side) it has.
+enum class OpKind { Generic, Whole51, Half51, Split };
+
+OpKind op_kind(const hub_ctx* c, int nrhs) {
+    if (c->path == HUB_PATH_SPLIT) return OpKind::Split;
+    if (c->L == 51 && c->specialized) return nrhs * c->Nt < kHalfBelow ? OpKind::Half51 : OpKind::Whole51;
+    return OpKind::Generic;
+}
+
+int op_slots(const hub_ctx* c, int nrhs) {
+    switch (op_kind(c, nrhs)) {
+        case OpKind::Half51: return 2 * c->Nt;
+        case OpKind::Split: return 2 * c->Nt * split_geom(c->L).nrb;
+        default: return c->Nt;
+    }
+}
+
 // Apply E between a source functor and an epilogue functor over nrhs right-hand sides.
-template <typename R, class Src, class Epi, class Fin>
-hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Fin& fin, int cid,
-                  hipStream_t st, const CgScalars* sc, int gate) {
+template <typename R, class Src, class Epi, class Ctl>
+hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ctl& ctl_in, hipStream_t st) {
     const OpTab<R> T = op_tab<R>(c);
-    RedArgs ra{c->partials, c->counters + cid, c->Nt, nrhs};
-    if (c->path == HUB_PATH_FUSED) {
-        const size_t lds = fused_lds<R>(c);
-        if (c->L == 51 && c->specialized) {
-            if (nrhs * c->Nt < kHalfBelow) {
-                // fewer slices than compute units: two workgroups per slice
-                ra.slots = 2 * c->Nt;
-                auto kern = k_fused_ct<R, 51, kThreads51, true, Src, Epi, Fin>;
-                allow_lds(kern, lds);
-                hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, fin, ra,
-                                   sc, gate);
-                return launch_check("k_fused_ct<51, half>");
-            }
-            auto kern = k_fused_ct<R, 51, kThreads51, false, Src, Epi, Fin>;
+    const OpKind kind = op_kind(c, nrhs);
+    const Ctl ctl = ctl_in.with_slots(op_slots(c, nrhs));
+    const size_t lds = fused_lds<R>(c);
+    switch (kind) {
+        case OpKind::Half51: {
+            auto kern = k_fused_ct<R, 51, kThreads51, true, Src, Epi, Ctl>;
             allow_lds(kern, lds);
-            hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, fin, ra, sc, gate);
+            hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
+            return launch_check("k_fused_ct<51, half>");
+        }
+        case OpKind::Whole51: {
+            auto kern = k_fused_ct<R, 51, kThreads51, false, Src, Epi, Ctl>;
+            allow_lds(kern, lds);
+            hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
             return launch_check("k_fused_ct<51>");
         }
-        auto kern = k_fused<R, Src, Epi, Fin>;
-        allow_lds(kern, lds);
-        hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads), lds, st, T, src, epi, fin, ra, sc, gate);
-        return launch_check("k_fused");
+        case OpKind::Generic: {
+            auto kern = k_fused<R, Src, Epi, Ctl>;
+            allow_lds(kern, lds);
+            hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads), lds, st, T, src, epi, ctl);
+            return launch_check("k_fused");
+        }
+        case OpKind::Split:
+            break;
     }
     const SplitGeom G = split_geom(c->L);
     cx<R>* W = reinterpret_cast<cx<R>*>(c->split_w);
     const size_t lds_rows = (size_t)(G.rb * c->L + c->L) * sizeof(cx<R>);
     const size_t lds_cols = (size_t)(2 * c->L * G.cb + c->L) * sizeof(cx<R>);
-    auto k1 = k_split_rows_fwd<R, Src>;
-    auto k2 = k_split_cols<R>;
-    auto k3 = k_split_rows_inv<R, Epi, Fin>;
+    auto k1 = k_split_rows_fwd<R, Src, Ctl>;
+    auto k2 = k_split_cols<R, Ctl>;
+    auto k3 = k_split_rows_inv<R, Epi, Ctl>;
     allow_lds(k1, lds_rows);
     allow_lds(k2, lds_cols);
     allow_lds(k3, lds_rows);
     const int nrow_blocks = nrhs * c->Nt * 2 * G.nrb;
-    hipLaunchKernelGGL(k1, dim3(nrow_blocks), dim3(kThreads), lds_rows, st, T, G, src, W, sc, gate);
+    hipLaunchKernelGGL(k1, dim3(nrow_blocks), dim3(kThreads), lds_rows, st, T, G, src, W, ctl);
     hub_status s = launch_check("k_split_rows_fwd");
     if (s != HUB_OK) return s;
-    hipLaunchKernelGGL(k2, dim3(nrhs * c->Nt * G.ncb), dim3(kThreads), lds_cols, st, T, G, W, sc, gate);
+    hipLaunchKernelGGL(k2, dim3(nrhs * c->Nt * G.ncb), dim3(kThreads), lds_cols, st, T, G, W, ctl);
     s = launch_check("k_split_cols");
     if (s != HUB_OK) return s;
-    ra.slots = c->Nt * 2 * G.nrb;
-    hipLaunchKernelGGL(k3, dim3(nrow_blocks), dim3(kThreads), lds_rows, st, T, G,
-                       static_cast<const cx<R>*>(W), epi, fin, ra, sc, gate);
+    hipLaunchKernelGGL(k3, dim3(nrow_blocks), dim3(kThreads), lds_rows, st, T, G, static_cast<const cx<R>*>(W),
+                       epi, ctl);
     return launch_check("k_split_rows_inv");
 }
 
@@ -162,8 +180,8 @@ hub_status apply_M_impl(hub_ctx* c, const R* phi, const void* in, void* out, int
     hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
-    return run_op<R>(c, nrhs, SrcPhasePrev<R>{v, PhAngle<R>{phi}}, EpiM<R>{v, static_cast<cx<R>*>(out)}, FinNone{}, 0,
-                     static_cast<hipStream_t>(stream), nullptr, GATE_NONE);
+    return run_op<R>(c, nrhs, SrcPhasePrev<R>{v, PhAngle<R>{phi}}, EpiM<R>{v, static_cast<cx<R>*>(out)},
+                     CtlPlain{}, static_cast<hipStream_t>(stream));
 }
 
 template <typename R>
@@ -171,8 +189,8 @@ hub_status apply_Mdag_impl(hub_ctx* c, const R* phi, const void* in, void* out, 
     hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
-    return run_op<R>(c, nrhs, SrcNext<R>{v}, EpiMdag<R>{v, static_cast<cx<R>*>(out), PhAngle<R>{phi}}, FinNone{}, 0,
-                     static_cast<hipStream_t>(stream), nullptr, GATE_NONE);
+    return run_op<R>(c, nrhs, SrcNext<R>{v}, EpiMdag<R>{v, static_cast<cx<R>*>(out), PhAngle<R>{phi}},
+                     CtlPlain{}, static_cast<hipStream_t>(stream));
 }
 
 hub_status ensure_cg_workspace(hub_ctx* c) {
@@ -187,6 +205,8 @@ hub_status ensure_cg_workspace(hub_ctx* c) {
     HIP_OR_FAIL(hipMalloc(&c->ph64, (size_t)c->N * sizeof(cx<double>)));
     HIP_OR_FAIL(hipMalloc(&c->ph32, (size_t)c->N * sizeof(cx<float>)));
     HIP_OR_FAIL(hipMalloc(&c->scal, (size_t)c->nrhs_max * sizeof(CgScalars)));
+    HIP_OR_FAIL(hipMalloc(&c->cg_pr, (size_t)3 * c->nrhs_max * c->max_partials * sizeof(double)));
+    HIP_OR_FAIL(hipMalloc(&c->cg_pt, (size_t)c->nrhs_max * c->max_partials * sizeof(double)));
     HIP_OR_FAIL(hipHostMalloc(&c->scal_host, (size_t)c->nrhs_max * sizeof(CgScalars), hipHostMallocDefault));
     c->cg_ready = true;
     return HUB_OK;
@@ -223,22 +243,29 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     const int zero_start = o.use_x0 ? 0 : 1;
     const int blocks = nrhs * c->Nt;
 
+    // ||r||^2 partials of iterations i, i-1, i+1 rotate through three buffers (index i mod 3)
+    const int slots = op_slots(c, nrhs);
+    auto pr = [&](long long i) { return c->cg_pr + (size_t)(i % 3) * nrhs * slots; };
+    double* pt = c->cg_pt;
+
     RedArgs ra{c->partials, c->counters + 1, c->Nt, nrhs};
     hipLaunchKernelGGL(k_cg_init<Rlo>, dim3(blocks), dim3(kThreads), 0, st, chi, xhi, rhi, xlo, rlo, p, c->V,
-                       c->Nt, zero_start, FinInit{sc, o.tol, zero_start}, ra);
+                       c->Nt, zero_start, FinInit{sc, o.tol, pr(0), pr(2), slots}, ra);
     hub_status s = launch_check("k_cg_init");
     if (s != HUB_OK) return s;
 
-    auto reliable_update = [&]() -> hub_status {
+    auto reliable_update = [&](long long i) -> hub_status {
         hipLaunchKernelGGL(k_fold_solution<Rlo>, dim3(512, nrhs), dim3(kThreads), 0, st, xhi, xlo, c->N,
                            static_cast<const CgScalars*>(sc));
         hub_status r = launch_check("k_fold_solution");
         if (r != HUB_OK) return r;
         r = run_op<double>(c, nrhs, SrcNext<double>{xhi}, EpiMdag<double, PhTable<double>>{xhi, tmp, tab64},
-                           FinNone{}, 2, st, sc, GATE_NOTDONE);
+                           CtlGate{sc, GATE_NOTDONE}, st);
         if (r != HUB_OK) return r;
+        const RedArgs red{c->partials, c->counters + 3, 0, nrhs};
         return run_op<double>(c, nrhs, SrcPhasePrev<double, PhTable<double>>{tmp, tab64},
-                              EpiResidual<Rlo>{tmp, chi, rhi, rlo}, FinResidual{sc}, 3, st, sc, GATE_NOTDONE);
+                              EpiResidual<Rlo>{tmp, chi, rhi, rlo},
+                              CtlAtomic<FinResidual>{sc, GATE_NOTDONE, red, FinResidual{sc, pr(i), pr(i + 2), slots}}, st);
     };
 
     if (!zero_start) {
@@ -246,7 +273,7 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
                            static_cast<const CgScalars*>(sc));
         s = launch_check("k_zero_trivial");
         if (s != HUB_OK) return s;
-        s = reliable_update();
+        s = reliable_update(0);
         if (s != HUB_OK) return s;
     }
 
@@ -272,16 +299,16 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
         }
         const long long n = std::min<long long>(every, o.max_iter - it);
         for (long long k = 0; k < n; ++k) {
-            s = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p, sc},
-                            EpiSearchMdag<Rlo, PhTable<Rlo>>{rlo, p, tv, tab_lo, sc}, FinSearch{sc}, 4, st, sc,
-                            GATE_ACTIVE);
+            const long long i = it + k;
+            s = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p}, EpiSearchMdag<Rlo, PhTable<Rlo>>{rlo, p, tv, tab_lo},
+                            CtlSearch{pr(i), pr(i + 2), pt, sc, slots}, st);
             if (s != HUB_OK) return s;
-            s = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhTable<Rlo>>{tv, tab_lo},
-                            EpiUpdate<Rlo>{tv, p, xlo, rlo, sc}, FinUpdate{sc}, 5, st, sc, GATE_ACTIVE);
+            s = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhTable<Rlo>>{tv, tab_lo}, EpiUpdate<Rlo>{tv, p, xlo, rlo},
+                            CtlUpdate{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots}, st);
             if (s != HUB_OK) return s;
         }
         it += n;
-        s = reliable_update();
+        s = reliable_update(it);
         if (s != HUB_OK) return s;
     }
     if (info) {
@@ -384,7 +411,7 @@ void hub_destroy(hub_ctx* c) {
     (void)hipDeviceSynchronize();
     void* dev[] = {c->roots64, c->roots32, c->etab64, c->etab32, c->partials, c->counters, c->red_out,
                    c->split_w, c->cg_rhi, c->cg_tmp, c->cg_x, c->cg_r, c->cg_p, c->cg_t,
-                   c->ph64, c->ph32, c->scal, c->force_tmp};
+                   c->ph64, c->ph32, c->scal, c->cg_pr, c->cg_pt, c->force_tmp};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->scal_host) (void)hipHostFree(c->scal_host);
@@ -431,11 +458,9 @@ hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     const cx<double>* xv = static_cast<const cx<double>*>(x);
     if (nrhs == 1)
-        return run_op<double>(c, 1, SrcNext<double>{xv}, EpiForce{xv, {phi}, g, 0}, FinNone{}, 0, st, nullptr,
-                              GATE_NONE);
+        return run_op<double>(c, 1, SrcNext<double>{xv}, EpiForce{xv, {phi}, g, 0}, CtlPlain{}, st);
     if (!c->force_tmp) HIP_OR_FAIL(hipMalloc(&c->force_tmp, (size_t)c->nrhs_max * c->N * sizeof(double)));
-    s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, {phi}, c->force_tmp, c->N}, FinNone{}, 0, st,
-                       nullptr, GATE_NONE);
+    s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, {phi}, c->force_tmp, c->N}, CtlPlain{}, st);
     if (s != HUB_OK) return s;
     hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, c->force_tmp, g, c->N, nrhs);
     return launch_check("k_sum_rhs");

@@ -46,7 +46,7 @@ struct CgScalars {
     double true_rr;   // ||chi - A x_hi||^2 at the last reliable update
     double tol2;      // tol^2 * ||chi||^2
     double rec_rr;    // iterated ||r||^2 just before the last reliable update
-    int32_t active;   // 1 while this right-hand side iterates
+    int32_t active;   // unused (kept for layout)
     int32_t done;     // 1 once the true residual met tol
     int32_t iters;
     int32_t reliable;
@@ -93,6 +93,8 @@ struct hub_ctx {
     void* ph64 = nullptr;        // e^{i phi} complex128 [Nt][V] for the solve in progress
     void* ph32 = nullptr;        // e^{i phi} complex64 [Nt][V]
     hub::CgScalars* scal = nullptr;      // device [nrhs_max]
+    double* cg_pr = nullptr;             // ||r||^2 partials, [3][nrhs_max][max_partials]
+    double* cg_pt = nullptr;             // ||M^dag p||^2 partials, [nrhs_max][max_partials]
     hub::CgScalars* scal_host = nullptr; // pinned host mirror
     double* force_tmp = nullptr;         // [nrhs_max][N] doubles, per-rhs force before summation
 };

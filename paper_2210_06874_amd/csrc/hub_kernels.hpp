@@ -50,6 +50,29 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return s;
 }
 
+// Block-wide sum in a fixed order, returned to every thread.
+__device__ __forceinline__ double block_allsum(double v, double* lds) {
+    const double s = block_sum(v, lds);
+    __shared__ double bcast;
+    if (threadIdx.x == 0) bcast = s;
+    __syncthreads();
+    return bcast;
+}
+
+// Sum of `n` partials in slot order, returned to every thread.
+__device__ __forceinline__ double sum_partials(const double* p, int n, double* lds) {
+    double v = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) v += p[j];
+    return block_allsum(v, lds);
+}
+
+// What an operator kernel's block learns before it starts: whether it works at all,
+// and the CG step scalars.
+struct Scal {
+    int open;
+    double alpha, beta;
+};
+
 // Store this block's partial, and let the block that arrives last sum every right-hand
 // side's partials in slot order and call fin(rhs, sum).  Deterministic: the final sums
 // never depend on arrival order.  `lds` needs 64 doubles.
@@ -86,13 +109,11 @@ __device__ __forceinline__ void reduce_and_finalize(double acc, int rhs, int slo
 }
 
 // ----------------------------------------------------------------------------- gating
-// CG kernels skip right-hand sides that are not iterating; gating is uniform per block.
-enum Gate : int { GATE_NONE = 0, GATE_ACTIVE = 1, GATE_NOTDONE = 2 };
+// Solver kernels skip right-hand sides whose solve is done; gating is uniform per block.
+enum Gate : int { GATE_NONE = 0, GATE_NOTDONE = 1 };
 
 __device__ __forceinline__ bool gate_open(const CgScalars* sc, int gate, int rhs) {
-    if (gate == GATE_NONE) return true;
-    if (gate == GATE_ACTIVE) return sc[rhs].active != 0;
-    return sc[rhs].done == 0;
+    return gate == GATE_NONE || sc[rhs].done == 0;
 }
 
 __device__ __forceinline__ int prev_slice(int t, int Nt) { return t == 0 ? Nt - 1 : t - 1; }
@@ -142,10 +163,7 @@ struct SrcPhasePrev {            // e^{i phi_{t-1}} v_{t-1}            (M)
         const long long k = (long long)ts * T.V + i;
         return {v[rhs * T.N + k], ph.fetch(k)};
     }
-    __device__ cx<R> make(const Pre& a, int) const { return cmul(a.v, ph.value(a.ph)); }
-    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
-        return make(fetch(rhs, ts, i, T), rhs);
-    }
+    __device__ cx<R> make(const Pre& a, const Scal&) const { return cmul(a.v, ph.value(a.ph)); }
 };
 
 template <typename R>
@@ -156,10 +174,7 @@ struct SrcNext {                 // v_{t+1}                            (M^dag, f
     __device__ Pre fetch(int rhs, int ts, int i, const OpTab<R>& T) const {
         return v[rhs * T.N + (long long)ts * T.V + i];
     }
-    __device__ cx<R> make(const Pre& a, int) const { return a; }
-    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
-        return make(fetch(rhs, ts, i, T), rhs);
-    }
+    __device__ cx<R> make(const Pre& a, const Scal&) const { return a; }
 };
 
 template <typename R>
@@ -172,18 +187,14 @@ struct SrcSearchNext {           // (r + beta p)_{t+1}                 (CG: M^da
     using Pre = PrePair<R>;
     const cx<R>* r;
     const cx<R>* p;
-    const CgScalars* sc;
     __device__ int slice(int t, int Nt) const { return next_slice(t, Nt); }
     __device__ Pre fetch(int rhs, int ts, int i, const OpTab<R>& T) const {
         const long long k = rhs * T.N + (long long)ts * T.V + i;
         return {r[k], p[k]};
     }
-    __device__ cx<R> make(const Pre& a, int rhs) const {
-        const R b = (R)sc[rhs].beta;
+    __device__ cx<R> make(const Pre& a, const Scal& s) const {
+        const R b = (R)s.beta;
         return {a.a.re + b * a.b.re, a.a.im + b * a.b.im};
-    }
-    __device__ cx<R> operator()(int rhs, int ts, int i, const OpTab<R>& T) const {
-        return make(fetch(rhs, ts, i, T), rhs);
     }
 };
 
@@ -199,7 +210,8 @@ struct EpiM {                    // out_t = v_t - B_t w
     __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
         return v[rhs * T.N + (long long)t * T.V + i];
     }
-    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, double&) const {
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, const Scal&,
+                          double&) const {
         out[rhs * T.N + (long long)t * T.V + i] = (t == 0) ? a + w : a - w;
     }
 };
@@ -214,7 +226,8 @@ struct EpiMdag {                 // out_t = v_t - B_{t+1} e^{-i phi_t} w
         const long long ks = (long long)t * T.V + i;
         return {v[rhs * T.N + ks], ph.fetch(ks)};
     }
-    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, double&) const {
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, const Scal&,
+                          double&) const {
         const cx<R> pw = cmulc(w, ph.value(a.ph));
         out[rhs * T.N + (long long)t * T.V + i] = (t == T.Nt - 1) ? a.v + pw : a.v - pw;
     }
@@ -233,14 +246,14 @@ struct EpiSearchMdag {           // CG: tv_t = (r + beta p)_t - B_{t+1} e^{-i ph
     const cx<R>* p;
     cx<R>* tv;
     Ph ph;
-    const CgScalars* sc;
     __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
         const long long ks = (long long)t * T.V + i;
         const long long k = rhs * T.N + ks;
         return {r[k], p[k], ph.fetch(ks)};
     }
-    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, double& acc) const {
-        const R b = (R)sc[rhs].beta;
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, const Scal& sc,
+                          double& acc) const {
+        const R b = (R)sc.beta;
         const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
         const cx<R> pw = cmulc(w, ph.value(a.ph));
         const cx<R> o = (t == T.Nt - 1) ? pn + pw : pn - pw;
@@ -261,15 +274,15 @@ struct EpiUpdate {               // CG: q = tv_t - B_t w; p = r + beta p; x += a
     cx<R>* p;
     cx<R>* x;
     cx<R>* r;
-    const CgScalars* sc;
     __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
         const long long k = rhs * T.N + (long long)t * T.V + i;
         return {tv[k], p[k], x[k], r[k]};
     }
-    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, double& acc) const {
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, const Scal& sc,
+                          double& acc) const {
         const long long k = rhs * T.N + (long long)t * T.V + i;
-        const R b = (R)sc[rhs].beta;
-        const R al = (R)sc[rhs].alpha;
+        const R b = (R)sc.beta;
+        const R al = (R)sc.alpha;
         const cx<R> q = (t == 0) ? a.tq + w : a.tq - w;
         const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
         const cx<R> rn = {a.r.re - al * q.re, a.r.im - al * q.im};
@@ -291,7 +304,7 @@ struct EpiResidual {             // FP64: r_hi = chi - (y_t - B_t w) with y = M^
         const long long k = rhs * T.N + (long long)t * T.V + i;
         return {y[k], chi[k]};
     }
-    __device__ void store(int rhs, int t, int i, cx<double> w, const Pre& a, const OpTab<double>& T,
+    __device__ void store(int rhs, int t, int i, cx<double> w, const Pre& a, const OpTab<double>& T, const Scal&,
                           double& acc) const {
         const long long k = rhs * T.N + (long long)t * T.V + i;
         const cx<double> q = (t == 0) ? a.a + w : a.a - w;
@@ -312,7 +325,7 @@ struct EpiForce {                // g_t = -2 B_{t+1} Im(e^{i phi_t} x_t conj(w))
         const long long ks = (long long)t * T.V + i;
         return {x[rhs * T.N + ks], ph.fetch(ks)};
     }
-    __device__ void store(int rhs, int t, int i, cx<double> w, const Pre& a, const OpTab<double>& T,
+    __device__ void store(int rhs, int t, int i, cx<double> w, const Pre& a, const OpTab<double>& T, const Scal&,
                           double&) const {
         const long long ks = (long long)t * T.V + i;
         const cx<double> z = cmulc(cmul(a.v, ph.value(a.ph)), w);
@@ -324,77 +337,59 @@ struct EpiForce {                // g_t = -2 B_{t+1} Im(e^{i phi_t} x_t conj(w))
 // fetch + store in one call (kernels that do not prefetch)
 template <typename R, class Epi>
 __device__ __forceinline__ void epi_apply(const Epi& epi, int rhs, int t, int i, cx<R> w, const OpTab<R>& T,
-                                          double& acc) {
-    epi.store(rhs, t, i, w, epi.fetch(rhs, t, i, T), T, acc);
+                                          const Scal& sc, double& acc) {
+    epi.store(rhs, t, i, w, epi.fetch(rhs, t, i, T), T, sc, acc);
+}
+
+template <typename R, class Src>
+__device__ __forceinline__ cx<R> src_apply(const Src& src, int rhs, int ts, int i, const OpTab<R>& T,
+                                           const Scal& sc) {
+    return src.make(src.fetch(rhs, ts, i, T), sc);
 }
 
 // ----------------------------------------------------------------------------- finalizers
-struct FinNone {
-    static constexpr bool kReduce = false;
-    __device__ void operator()(int, double) const {}
-};
-
-struct FinSearch {               // alpha = rr / ||M^dag p||^2
-    static constexpr bool kReduce = true;
+// Called by thread 0 of the block that arrives last, once per right-hand side in order.
+struct FinResidual {             // after an FP64 residual recomputation (CG reliable update)
     CgScalars* sc;
-    __device__ void operator()(int r, double tt) const {
-        if (!sc[r].active) return;
-        sc[r].tt = tt;
-        const double a = sc[r].rr / tt;
-        if (!(tt > 0.0) || !isfinite(a)) {
-            sc[r].nonfinite = 1;
-            sc[r].active = 0;
-            return;
-        }
-        sc[r].alpha = a;
-    }
-};
-
-struct FinUpdate {               // beta = rr'/rr; stop iterating once the iterated residual meets tol
-    static constexpr bool kReduce = true;
-    CgScalars* sc;
-    __device__ void operator()(int r, double rr) const {
-        if (!sc[r].active) return;
-        sc[r].iters += 1;
-        if (!isfinite(rr)) {
-            sc[r].nonfinite = 1;
-            sc[r].active = 0;
-            return;
-        }
-        sc[r].beta = rr / sc[r].rr;
-        sc[r].rr = rr;
-        if (rr <= sc[r].tol2) sc[r].active = 0;
-    }
-};
-
-struct FinResidual {             // after an FP64 residual recomputation
-    static constexpr bool kReduce = true;
-    CgScalars* sc;
+    double* rr_cur;              // ||r||^2 partials the next CG iteration starts from, [nrhs][slots]
+    double* rr_prev;             // and those of the iteration before
+    int slots;
     __device__ void operator()(int r, double rr) const {
         if (sc[r].done) return;
+        double* cur = rr_cur + (long long)r * slots;
+        double* prev = rr_prev + (long long)r * slots;
+        double rec = 0.0, old = 0.0;
+        for (int j = 0; j < slots; ++j) {
+            rec += cur[j];
+            old += prev[j];
+        }
         sc[r].reliable += 1;
-        sc[r].rec_rr = sc[r].rr;
+        sc[r].rec_rr = rec;
         sc[r].true_rr = rr;
         if (!isfinite(rr)) {
             sc[r].nonfinite = 1;
-            sc[r].active = 0;
             return;
         }
         sc[r].rr = rr;
-        if (rr <= sc[r].tol2) {
-            sc[r].done = 1;
-            sc[r].active = 0;
-        } else if (!sc[r].nonfinite) {
-            sc[r].active = 1;
+        // The iteration continues from the recomputed residual: alpha uses ||r_true||^2,
+        // while the search direction keeps the recursion's beta = rec / old (the previous
+        // entry is rescaled so that the ratio the next kernel forms is unchanged).
+        cur[0] = rr;
+        for (int j = 1; j < slots; ++j) cur[j] = 0.0;
+        if (rec > 0.0 && isfinite(rec)) {
+            prev[0] = old * (rr / rec);
+            for (int j = 1; j < slots; ++j) prev[j] = 0.0;
         }
+        if (rr <= sc[r].tol2) sc[r].done = 1;
     }
 };
 
 struct FinInit {                 // ||chi||^2 and the starting state of every right-hand side
-    static constexpr bool kReduce = true;
     CgScalars* sc;
     double tol;
-    int start_from_zero;
+    double* rr0;                 // ||r||^2 partials of iteration 0, [nrhs][slots]
+    double* rr_prev;             // and of "iteration -1" (only their ratio with rr0 is used, times p = 0)
+    int slots;
     __device__ void operator()(int r, double cc) const {
         CgScalars s{};
         s.chichi = cc;
@@ -402,23 +397,125 @@ struct FinInit {                 // ||chi||^2 and the starting state of every ri
         s.rr = cc;
         s.true_rr = cc;
         s.rec_rr = cc;
-        s.beta = 0.0;
-        s.alpha = 0.0;
         s.nonfinite = isfinite(cc) ? 0 : 1;
         s.done = (cc == 0.0) ? 1 : 0;
-        s.active = (start_from_zero && !s.done && !s.nonfinite) ? 1 : 0;
         sc[r] = s;
+        rr0[(long long)r * slots] = cc;
+        rr_prev[(long long)r * slots] = cc;
+        for (int j = 1; j < slots; ++j) {
+            rr0[(long long)r * slots + j] = 0.0;
+            rr_prev[(long long)r * slots + j] = 0.0;
+        }
     }
 };
 
 struct FinStore {                // out[0] = sum over right-hand sides (in order)
-    static constexpr bool kReduce = true;
     double* out;
     int nrhs;
     __device__ void operator()(int r, double v) const {
-        // called for r = 0..nrhs-1 in order by one thread
         out[0] = (r == 0) ? v : out[0] + v;
     }
+};
+
+// ----------------------------------------------------------------------------- block control
+// An operator kernel asks its control policy, before anything else, whether the block
+// works and with which CG scalars (begin), and hands it the block's reduction value at
+// the end (end).  begin() and end() are called by every thread of the block.
+struct CtlPlain {                // operators and force: always work, nothing reduced
+    static constexpr bool kEnd = false;
+    __device__ Scal begin(int, int, double*) const { return {1, 0.0, 0.0}; }
+    __device__ void end(double, int, int, const Scal&, double*) const {}
+    CtlPlain with_slots(int) const { return *this; }
+};
+
+struct CtlGate {                 // gate from the CG scalars, nothing reduced
+    static constexpr bool kEnd = false;
+    const CgScalars* sc;
+    int gate;
+    __device__ Scal begin(int rhs, int, double*) const { return {gate_open(sc, gate, rhs) ? 1 : 0, 0.0, 0.0}; }
+    __device__ void end(double, int, int, const Scal&, double*) const {}
+    CtlGate with_slots(int) const { return *this; }
+};
+
+template <class Fin>
+struct CtlAtomic {               // gate from the CG scalars; last-block finalize of the reduction
+    static constexpr bool kEnd = true;
+    const CgScalars* sc;
+    int gate;
+    RedArgs ra;
+    Fin fin;
+    __device__ Scal begin(int rhs, int, double*) const { return {gate_open(sc, gate, rhs) ? 1 : 0, 0.0, 0.0}; }
+    __device__ void end(double acc, int rhs, int slot, const Scal&, double* lds) const {
+        reduce_and_finalize(acc, rhs, slot, ra, fin, lds);
+    }
+    CtlAtomic with_slots(int n) const {
+        CtlAtomic c = *this;
+        c.ra.slots = n;
+        return c;
+    }
+};
+
+// CG iteration i, first kernel: t = M^dag (r + beta p).  beta = rr_i / rr_{i-1} from the
+// previous kernels' partials (summed in slot order by every block, so every block
+// agrees); the block works while ||r_i||^2 > tol^2 ||chi||^2 and the solve is not done.
+// Writes this block's partial of ||t||^2.
+struct CtlSearch {
+    static constexpr bool kEnd = true;
+    const double* rr_i;          // [nrhs][slots]
+    const double* rr_im1;
+    double* tt_out;
+    CgScalars* sc;
+    int slots;
+    __device__ Scal begin(int rhs, int slot, double* lds) const {
+        const double a = sum_partials(rr_i + (long long)rhs * slots, slots, lds);
+        const double b = sum_partials(rr_im1 + (long long)rhs * slots, slots, lds);
+        const CgScalars& s = sc[rhs];
+        int open = (!s.done && !s.nonfinite && a > s.tol2) ? 1 : 0;
+        const double beta = a / b;
+        if (open && !isfinite(beta)) {
+            open = 0;
+            if (slot == 0 && threadIdx.x == 0) sc[rhs].nonfinite = 1;
+        }
+        return {open, 0.0, beta};
+    }
+    __device__ void end(double acc, int rhs, int slot, const Scal&, double* lds) const {
+        const double v = block_sum(acc, lds);
+        if (threadIdx.x == 0) tt_out[(long long)rhs * slots + slot] = v;
+    }
+    CtlSearch with_slots(int) const { return *this; }
+};
+
+// CG iteration i, second kernel: q = M t, p = r + beta p, x += alpha p, r -= alpha q,
+// alpha = rr_i / ||t||^2.  Writes this block's partial of ||r_{i+1}||^2, or carries the
+// block's rr_i partial forward when the block is idle (so an idle solve stays idle).
+struct CtlUpdate {
+    static constexpr bool kEnd = true;
+    const double* rr_i;
+    const double* rr_im1;
+    const double* tt;
+    double* rr_next;
+    CgScalars* sc;
+    int slots;
+    __device__ Scal begin(int rhs, int slot, double* lds) const {
+        const double a = sum_partials(rr_i + (long long)rhs * slots, slots, lds);
+        const double b = sum_partials(rr_im1 + (long long)rhs * slots, slots, lds);
+        const double c = sum_partials(tt + (long long)rhs * slots, slots, lds);
+        const CgScalars& s = sc[rhs];
+        int open = (!s.done && !s.nonfinite && a > s.tol2) ? 1 : 0;
+        const double alpha = a / c, beta = a / b;
+        if (open && (!(c > 0.0) || !isfinite(alpha) || !isfinite(beta))) {
+            open = 0;
+            if (slot == 0 && threadIdx.x == 0) sc[rhs].nonfinite = 1;
+        }
+        if (open && slot == 0 && threadIdx.x == 0) sc[rhs].iters += 1;
+        return {open, alpha, beta};
+    }
+    __device__ void end(double acc, int rhs, int slot, const Scal& s, double* lds) const {
+        const double v = block_sum(acc, lds);
+        const long long k = (long long)rhs * slots + slot;
+        if (threadIdx.x == 0) rr_next[k] = s.open ? v : rr_i[k];
+    }
+    CtlUpdate with_slots(int) const { return *this; }
 };
 
 // ----------------------------------------------------------------------------- fused kernel
@@ -444,10 +541,9 @@ __device__ __forceinline__ void mix_E(cx<R>* A, cx<R>* B, int LL, const R* __res
     }
 }
 
-template <typename R, class Src, class Epi, class Fin>
+template <typename R, class Src, class Epi, class Ctl>
 __global__ void __launch_bounds__(kThreads)
-k_fused(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const RedArgs ra,
-        const CgScalars* sc, int gate) {
+k_fused(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red_lds[64];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
@@ -455,11 +551,12 @@ k_fused(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const Red
     const int L = T.L, LL = L * L, V = T.V;
     const int u = xcd_linear(blockIdx.x, gridDim.x);
     const int rhs = u / T.Nt, t = u - rhs * T.Nt;
+    const Scal sc = ctl.begin(rhs, t, red_lds);
     double acc = 0.0;
-    if (gate_open(sc, gate, rhs)) {
+    if (sc.open) {
         for (int i = threadIdx.x; i < L; i += blockDim.x) roots[i] = T.roots[i];
         const int ts = src.slice(t, T.Nt);
-        for (int i = threadIdx.x; i < V; i += blockDim.x) buf[i] = src(rhs, ts, i, T);
+        for (int i = threadIdx.x; i < V; i += blockDim.x) buf[i] = src_apply(src, rhs, ts, i, T, sc);
         __syncthreads();
         const LineMap rows{1, L, 0, 1};
         const LineMap cols{L, LL, 1, L};
@@ -469,9 +566,9 @@ k_fused(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const Red
         __syncthreads();
         fft_lines<R, true>(buf, cols, 2 * L, T.plan, roots);
         fft_lines<R, true>(buf, rows, 2 * L, T.plan, roots);
-        for (int i = threadIdx.x; i < V; i += blockDim.x) epi_apply(epi, rhs, t, i, buf[i], T, acc);
+        for (int i = threadIdx.x; i < V; i += blockDim.x) epi_apply(epi, rhs, t, i, buf[i], T, sc, acc);
     }
-    if constexpr (Fin::kReduce) reduce_and_finalize(acc, rhs, t, ra, fin, red_lds);
+    if constexpr (Ctl::kEnd) ctl.end(acc, rhs, t, sc, red_lds);
 }
 
 // Same layout with L known at compile time (NT threads per workgroup).  The first
@@ -490,10 +587,9 @@ struct EpiPrefetchFits {
     static constexpr bool value = BYTES <= 400;   // register budget per thread
 };
 
-template <typename R, int L, int NT, bool HALF, class Src, class Epi, class Fin>
+template <typename R, int L, int NT, bool HALF, class Src, class Epi, class Ctl>
 __global__ void __launch_bounds__(NT)
-k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const RedArgs ra,
-           const CgScalars* sc, int gate) {
+k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     constexpr CPlan P = make_cplan(L);
     static_assert(P.nst >= 1, "L = 1 takes the generic kernel");
     constexpr int LL = L * L, V = 2 * LL;
@@ -513,9 +609,11 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const 
     const int h = HALF ? (u & 1) : 0;                   // sublattice written (HALF only)
     const int rhs = q / T.Nt, t = q - rhs * T.Nt;
     const int off = HALF ? h * LL : 0;                  // first site written
+    const int slot = HALF ? 2 * t + h : t;
     const int tid = threadIdx.x;
+    const Scal sc = ctl.begin(rhs, slot, red_lds);
     double acc = 0.0;
-    if (gate_open(sc, gate, rhs)) {
+    if (sc.open) {
         const int ts = src.slice(t, T.Nt);
         // issue every global load of the source and of E(k)
         typename Src::Pre pre[ROUNDS0][R0];
@@ -549,7 +647,7 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const 
                 const int base = line * L + np;
                 cx<R> x[R0];
 #pragma unroll
-                for (int i = 0; i < R0; ++i) x[i] = src.make(pre[rd][i], rhs);
+                for (int i = 0; i < R0; ++i) x[i] = src.make(pre[rd][i], sc);
                 small_dft_ct<R, R0, false>(x);
                 if constexpr (M0 > 1) {
 #pragma unroll
@@ -610,13 +708,13 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Fin fin, const 
                 small_dft_ct<R, R0, true>(x);
 #pragma unroll
                 for (int i = 0; i < R0; ++i) {
-                    if constexpr (kPreEpi) epi.store(rhs, t, off + base + i * M0, x[i], ep[rd][i], T, acc);
-                    else epi_apply(epi, rhs, t, off + base + i * M0, x[i], T, acc);
+                    if constexpr (kPreEpi) epi.store(rhs, t, off + base + i * M0, x[i], ep[rd][i], T, sc, acc);
+                    else epi_apply(epi, rhs, t, off + base + i * M0, x[i], T, sc, acc);
                 }
             }
         }
     }
-    if constexpr (Fin::kReduce) reduce_and_finalize(acc, rhs, HALF ? 2 * t + h : t, ra, fin, red_lds);
+    if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
 }
 
 // e^{i phi} as a table, evaluated in FP64 and rounded once to R
@@ -640,11 +738,11 @@ struct SplitGeom {
     int cb, ncb;      // columns per block, column blocks
 };
 
-template <typename R, class Src>
+template <typename R, class Src, class Ctl>
 __global__ void __launch_bounds__(kThreads)
-k_split_rows_fwd(const OpTab<R> T, const SplitGeom G, const Src src, cx<R>* __restrict__ W,
-                 const CgScalars* sc, int gate) {
+k_split_rows_fwd(const OpTab<R> T, const SplitGeom G, const Src src, cx<R>* __restrict__ W, const Ctl ctl) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
     const int L = T.L;
     cx<R>* roots = buf + G.rb * L;
@@ -653,31 +751,34 @@ k_split_rows_fwd(const OpTab<R> T, const SplitGeom G, const Src src, cx<R>* __re
     const int s = b % 2; b /= 2;
     const int t = b % T.Nt;
     const int rhs = b / T.Nt;
-    if (!gate_open(sc, gate, rhs)) return;
+    const Scal sc = ctl.begin(rhs, -1, red_lds);
+    if (!sc.open) return;
     const int r0 = rblk * G.rb;
     const int nr = min(G.rb, L - r0);
     for (int i = threadIdx.x; i < L; i += blockDim.x) roots[i] = T.roots[i];
     const int ts = src.slice(t, T.Nt);
     const int off = s * L * L + r0 * L;
-    for (int i = threadIdx.x; i < nr * L; i += blockDim.x) buf[i] = src(rhs, ts, off + i, T);
+    for (int i = threadIdx.x; i < nr * L; i += blockDim.x) buf[i] = src_apply(src, rhs, ts, off + i, T, sc);
     __syncthreads();
     fft_lines<R, false>(buf, LineMap{1, L, 0, 1}, nr, T.plan, roots);
     cx<R>* dst = W + rhs * T.N + (long long)t * T.V + off;
     for (int i = threadIdx.x; i < nr * L; i += blockDim.x) dst[i] = buf[i];
 }
 
-template <typename R>
+template <typename R, class Ctl>
 __global__ void __launch_bounds__(kThreads)
-k_split_cols(const OpTab<R> T, const SplitGeom G, cx<R>* __restrict__ W, const CgScalars* sc, int gate) {
+k_split_cols(const OpTab<R> T, const SplitGeom G, cx<R>* __restrict__ W, const Ctl ctl) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
-    const int L = T.L, LL = L * L;
+    const int L = T.L;
     cx<R>* roots = buf + 2 * L * G.cb;
     int b = blockIdx.x;
     const int cblk = b % G.ncb; b /= G.ncb;
     const int t = b % T.Nt;
     const int rhs = b / T.Nt;
-    if (!gate_open(sc, gate, rhs)) return;
+    const Scal sc = ctl.begin(rhs, -1, red_lds);
+    if (!sc.open) return;
     const int c0 = cblk * G.cb;
     const int nc = min(G.cb, L - c0);
     for (int i = threadIdx.x; i < L; i += blockDim.x) roots[i] = T.roots[i];
@@ -704,13 +805,12 @@ k_split_cols(const OpTab<R> T, const SplitGeom G, cx<R>* __restrict__ W, const C
         const int c = i % nc, sn = i / nc;
         base[(long long)sn * L + c0 + c] = buf[i];
     }
-    (void)LL;
 }
 
-template <typename R, class Epi, class Fin>
+template <typename R, class Epi, class Ctl>
 __global__ void __launch_bounds__(kThreads)
 k_split_rows_inv(const OpTab<R> T, const SplitGeom G, const cx<R>* __restrict__ W, const Epi epi,
-                 const Fin fin, const RedArgs ra, const CgScalars* sc, int gate) {
+                 const Ctl ctl) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red_lds[64];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
@@ -722,8 +822,9 @@ k_split_rows_inv(const OpTab<R> T, const SplitGeom G, const cx<R>* __restrict__ 
     const int s = b % 2; b /= 2;
     const int t = b % T.Nt;
     const int rhs = b / T.Nt;
+    const Scal sc = ctl.begin(rhs, slot, red_lds);
     double acc = 0.0;
-    if (gate_open(sc, gate, rhs)) {
+    if (sc.open) {
         const int r0 = rblk * G.rb;
         const int nr = min(G.rb, L - r0);
         for (int i = threadIdx.x; i < L; i += blockDim.x) roots[i] = T.roots[i];
@@ -732,9 +833,9 @@ k_split_rows_inv(const OpTab<R> T, const SplitGeom G, const cx<R>* __restrict__ 
         for (int i = threadIdx.x; i < nr * L; i += blockDim.x) buf[i] = srcp[i];
         __syncthreads();
         fft_lines<R, true>(buf, LineMap{1, L, 0, 1}, nr, T.plan, roots);
-        for (int i = threadIdx.x; i < nr * L; i += blockDim.x) epi_apply(epi, rhs, t, off + i, buf[i], T, acc);
+        for (int i = threadIdx.x; i < nr * L; i += blockDim.x) epi_apply(epi, rhs, t, off + i, buf[i], T, sc, acc);
     }
-    if constexpr (Fin::kReduce) reduce_and_finalize(acc, rhs, slot, ra, fin, red_lds);
+    if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
 }
 
 // ----------------------------------------------------------------------------- elementwise kernels
