@@ -34,7 +34,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "M-applications/s & s per HMC force, L=51 Nt=128, FP32-mixed vs FP64 @1e-10 res"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_M_c64_L51_Nt128.txt")
-KERNEL_SOURCES = ["hub_fft.hpp", "hub_kernels.hpp", "hub_abi.hip", "hub_tables.cpp", "hub_internal.hpp"]
+KERNEL_SOURCES = ["hub_fft.hpp", "hub_kernels.hpp", "hub_math.hpp", "hub_abi.hip", "hub_tables.cpp",
+                  "hub_tables.hpp", "hub_internal.hpp"]
 
 
 def kernel_hash() -> str:

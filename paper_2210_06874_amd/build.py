@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhubhip.so")
 
 SOURCES = ["hub_abi.hip", "hub_tables.cpp"]
-HEADERS = ["hub_internal.hpp", "hub_fft.hpp", "hub_kernels.hpp"]
+HEADERS = ["hub_internal.hpp", "hub_tables.hpp", "hub_fft.hpp", "hub_kernels.hpp", "hub_math.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -8,7 +8,7 @@
 //     exp(dk K(k)) = cosh(dk|f|) 1 + sinh(dk|f|)/|f| K(k).
 #include <cmath>
 
-#include "hub_internal.hpp"
+#include "hub_tables.hpp"
 
 namespace hub {
 

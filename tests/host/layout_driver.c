@@ -1,0 +1,18 @@
+/* Prints sizeof/offsetof of the ABI structs as the C compiler lays them out. */
+#include <stddef.h>
+#include <stdio.h>
+
+#include "hub.h"
+
+int main(void) {
+    printf("hub_params %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hub_params), offsetof(hub_params, L),
+           offsetof(hub_params, Nt), offsetof(hub_params, beta), offsetof(hub_params, kappa),
+           offsetof(hub_params, nrhs_max), offsetof(hub_params, path));
+    printf("hub_cg_opts %zu %zu %zu %zu %zu %zu\n", sizeof(hub_cg_opts), offsetof(hub_cg_opts, tol),
+           offsetof(hub_cg_opts, max_iter), offsetof(hub_cg_opts, reliable_every), offsetof(hub_cg_opts, prec),
+           offsetof(hub_cg_opts, use_x0));
+    printf("hub_cg_info %zu %zu %zu %zu %zu\n", sizeof(hub_cg_info), offsetof(hub_cg_info, iters),
+           offsetof(hub_cg_info, reliable_updates), offsetof(hub_cg_info, true_rel_res),
+           offsetof(hub_cg_info, recursive_rel_res));
+    return 0;
+}

@@ -1,0 +1,140 @@
+"""CPU checks of the C ABI and of the host-side logic (no device calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hub.h")
+CSRC = os.path.join(ROOT, "paper_2210_06874_amd", "csrc")
+
+
+def _lib():
+    from paper_2210_06874_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libhubhip.so not built (run __graft_entry__.build())")
+    return L, L.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hub_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L, lib = _lib()
+    names = declared_functions()
+    assert {"hub_apply_M", "hub_apply_Mdag", "hub_cg_solve", "hub_force"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (hub_\w+)", out))
+    assert set(names) <= exported, set(names) - exported
+    assert set(names) == set(L.SIGNATURES), "binding and header disagree"
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    L, _ = _lib()
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "host", "layout_driver.c"), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines()
+    got = {ln.split()[0]: list(map(int, ln.split()[1:])) for ln in lines}
+    for cname, cls in (("hub_params", L.HubParams), ("hub_cg_opts", L.HubCgOpts), ("hub_cg_info", L.HubCgInfo)):
+        ref = [ctypes.sizeof(cls)] + [getattr(cls, f[0]).offset for f in cls._fields_]
+        assert got[cname] == ref, (cname, got[cname], ref)
+
+
+def test_argument_errors_before_any_device_call():
+    L, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.hub_create(None, None, ctypes.byref(h)) == L.HUB_ERR_ARG
+    assert b"NULL" in lib.hub_last_error()
+    for bad in [dict(L=0), dict(L=19), dict(L=2048), dict(Nt=0), dict(nrhs_max=0), dict(path=7),
+                dict(beta=float("nan"))]:
+        prm = dict(L=3, Nt=8, beta=2.0, kappa=1.0, nrhs_max=1, path=0)
+        prm.update(bad)
+        p = L.HubParams(prm["L"], prm["Nt"], prm["beta"], prm["kappa"], prm["nrhs_max"], prm["path"])
+        assert lib.hub_create(ctypes.byref(p), None, ctypes.byref(h)) == L.HUB_ERR_ARG, bad
+        assert h.value is None
+    assert lib.hub_create(ctypes.byref(L.HubParams(3, 8, 2.0, 1.0, 1, 0)), None, None) == L.HUB_ERR_ARG
+    x = ctypes.c_void_p(1)
+    assert lib.hub_apply_M(None, x, x, x, 1, None) == L.HUB_ERR_ARG
+    assert lib.hub_apply_Mdag(None, x, x, x, 1, None) == L.HUB_ERR_ARG
+    assert lib.hub_force(None, x, x, x, 1, None) == L.HUB_ERR_ARG
+    assert lib.hub_action(None, x, x, 1, x, None) == L.HUB_ERR_ARG
+    opts = L.HubCgOpts(1e-10, 100, 50, 0, 0)
+    assert lib.hub_cg_solve(None, x, x, x, 1, ctypes.byref(opts), None, None) == L.HUB_ERR_ARG
+    assert lib.hub_query(None, None, None) == L.HUB_ERR_ARG
+    lib.hub_destroy(None)   # no-op
+
+
+# ----------------------------------------------------------------------------- host tables
+def _tables(tmp_path, L, dk):
+    exe = tmp_path / "tables"
+    if not exe.exists():
+        subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, os.path.join(ROOT, "tests", "host", "tables_driver.cpp"),
+                        os.path.join(CSRC, "hub_tables.cpp"), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe), str(L), repr(dk)], capture_output=True, text=True, check=True).stdout
+    lines = out.splitlines()
+    if lines[0] == "noplan":
+        return None
+    plan = list(map(int, lines[0].split()[1:]))[1:]
+    pos = list(map(int, lines[1].split()[1:]))
+    roots = np.array([[float(a) for a in ln.split()[1:]] for ln in lines if ln.startswith("root")])
+    etab = np.array([[float(a) for a in ln.split()[1:]] for ln in lines if ln.startswith("e ")])
+    return plan, pos, roots[:, 0] + 1j * roots[:, 1], etab
+
+
+def _dif(x, plan):
+    """In-place decimation-in-frequency stages with the plan's radices (reference model)."""
+    L = len(x)
+    x = x.astype(complex).copy()
+    w = np.exp(-2j * np.pi * np.arange(L) / L)
+    Lq = L
+    for r in plan:
+        m = Lq // r
+        for blk in range(L // Lq):
+            for n in range(m):
+                idx = blk * Lq + n + m * np.arange(r)
+                y = np.exp(-2j * np.pi * np.outer(np.arange(r), np.arange(r)) / r) @ x[idx]
+                x[idx] = y * w[(n * np.arange(r) * (L // Lq)) % L]
+        Lq = m
+    return x
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 12, 24, 51, 102, 7 * 5, 17])
+def test_plan_positions_follow_the_transform(tmp_path, L):
+    """The digit-reversed position table is where the in-place transform leaves each
+    frequency (checked against numpy's FFT)."""
+    plan, pos, roots, _ = _tables(tmp_path, L, 0.1)
+    assert int(np.prod(plan)) == L and set(plan) <= {2, 3, 4, 5, 7, 11, 13, 17}
+    assert sorted(pos) == list(range(L))
+    x = np.random.default_rng(L).normal(size=L) + 1j * np.random.default_rng(L + 1).normal(size=L)
+    y = _dif(x, plan)
+    np.testing.assert_allclose(y[pos], np.fft.fft(x), atol=1e-9 * np.abs(x).sum())
+    np.testing.assert_allclose(roots, np.exp(-2j * np.pi * np.arange(L) / L), atol=2e-16)
+
+
+@pytest.mark.parametrize("L,dk", [(3, 0.25), (12, 0.125), (51, 0.0625), (6, 1.5)])
+def test_momentum_hopping_table_is_the_2x2_exponential(tmp_path, L, dk):
+    """E(k)/L^2 at every transform position equals scipy's expm of dk [[0, f], [conj f, 0]]."""
+    plan, pos, _, etab = _tables(tmp_path, L, dk)
+    inv = np.empty(L, dtype=int)
+    inv[pos] = np.arange(L)
+    for p1 in range(L):
+        for p2 in range(L):
+            k1, k2 = 2 * np.pi * inv[p1] / L, 2 * np.pi * inv[p2] / L
+            f = 1 + np.exp(-1j * k1) + np.exp(-1j * k2)
+            E = scipy.linalg.expm(dk * np.array([[0, f], [np.conj(f), 0]]))
+            c, sr, si = etab[p1 * L + p2] * L * L
+            np.testing.assert_allclose([c, sr + 1j * si], [E[0, 0].real, E[0, 1]], atol=5e-15)
+            np.testing.assert_allclose(E[1, 0], sr - 1j * si, atol=5e-15)
+
+
+def test_unsupported_lengths_have_no_plan(tmp_path):
+    assert _tables(tmp_path, 19, 0.1) is None
+    assert _tables(tmp_path, 23 * 2, 0.1) is None
