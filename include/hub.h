@@ -138,6 +138,20 @@ hub_status hub_force(hub_ctx* ctx, const double* phi, const void* x, double* dSd
 hub_status hub_action(hub_ctx* ctx, const void* chi, const void* x, int32_t nrhs,
                       double* S_dev, void* stream);
 
+/* One molecular-dynamics update of an HMC trajectory (Sec. 2: phi evolves with the
+ * momentum pi under H = pi^2/2 + phi^2/(2 delta U) + S_f[phi]).  With the total force
+ * F = phi/(delta U) + dSdphi (dSdphi from hub_force):  pi -= eps_pi * F,  then
+ * phi += eps_phi * pi.  phi, pi, dSdphi: double [Nt][V] on the device, not overlapping;
+ * phi and pi are updated in place.  A leapfrog step is (eps/2, eps), (eps, eps), ...,
+ * (eps/2, 0).  U > 0. */
+hub_status hub_md_update(hub_ctx* ctx, double* phi, double* pi, const double* dSdphi, double U,
+                         double eps_pi, double eps_phi, void* stream);
+
+/* out_dev[0] = sum pi^2/2 + sum phi^2/(2 delta U) in FP64: the bosonic part of the HMC
+ * Hamiltonian of eq. "hamiltonian" (its fermionic part is hub_action).  One double on the device. */
+hub_status hub_boson_energy(hub_ctx* ctx, const double* phi, const double* pi, double U, double* out_dev,
+                            void* stream);
+
 /* Report the kernel path the context uses (hub_path value, never AUTO) and the
  * LDS bytes per workgroup of its operator kernel. */
 hub_status hub_query(const hub_ctx* ctx, int32_t* path, int32_t* lds_bytes);

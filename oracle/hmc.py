@@ -1,0 +1,55 @@
+"""FP64 CPU oracle of one HMC trajectory (Sec. 2).  TEST INFRASTRUCTURE ONLY.
+
+Hamiltonian (eq. "hamiltonian", with phi = delta * the paper's field):
+    H = sum pi^2/2 + sum phi^2/(2 delta U) + chi^dag (M M^dag)^{-1} chi.
+The trajectory draws nothing itself: the momenta pi0, the heat-bath vector rho
+(chi = M rho) and the Metropolis uniform u are inputs.  Molecular dynamics is the
+leapfrog (half momentum step, alternating full steps, half momentum step); the
+trajectory is accepted with probability min(1, e^{-dH}).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .hubbard import HubbardOperator, cg_solve, dense_solve, action, force
+
+
+def _solve(op, phi, chi, tol, dense):
+    if dense:
+        return dense_solve(op, phi, chi)
+    x, _, _ = cg_solve(op, phi, chi, tol=tol)
+    return x
+
+
+def hamiltonian(op: HubbardOperator, U: float, phi, pi, chi, x) -> float:
+    return 0.5 * float(np.sum(pi * pi)) + float(np.sum(phi * phi)) / (2.0 * op.delta * U) + action(chi, x)
+
+
+def total_force(op: HubbardOperator, U: float, phi, x) -> np.ndarray:
+    """dH/dphi = phi/(delta U) + dS_f/dphi."""
+    return phi / (op.delta * U) + force(op, phi, x)
+
+
+def trajectory(op: HubbardOperator, U: float, phi0, pi0, rho, u: float, n_md: int, eps: float,
+               tol: float = 1e-12, dense: bool | None = None):
+    """Returns (phi_end, pi_end, dH, accepted, phi_out) with phi_out = phi_end if accepted
+    else phi0."""
+    if dense is None:
+        dense = op.N <= 2000
+    phi = np.array(phi0, dtype=float)
+    pi = np.array(pi0, dtype=float)
+    chi = op.apply_M(phi, rho)
+    x = _solve(op, phi, chi, tol, dense)
+    H0 = hamiltonian(op, U, phi, pi, chi, x)
+    pi = pi - 0.5 * eps * total_force(op, U, phi, x)
+    for s in range(n_md):
+        phi = phi + eps * pi
+        x = _solve(op, phi, chi, tol, dense)
+        step = eps if s < n_md - 1 else 0.5 * eps
+        pi = pi - step * total_force(op, U, phi, x)
+    H1 = hamiltonian(op, U, phi, pi, chi, x)
+    dH = H1 - H0
+    accepted = bool(dH <= 0.0 or u < math.exp(-dH))
+    return phi, pi, dH, accepted, (phi if accepted else np.array(phi0, dtype=float))

@@ -171,4 +171,24 @@ class Hubbard:
         return S
 
 
+    # ------------------------------------------------------------------ HMC pieces
+    def md_update(self, phi, pi, dSdphi, U: float, eps_pi: float, eps_phi: float):
+        """In place: pi -= eps_pi (phi/(delta U) + dSdphi); phi += eps_phi pi."""
+        for a in (phi, pi, dSdphi):
+            self._phi(a)
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_md_update(self._h, self._p(phi), self._p(pi), self._p(dSdphi), float(U),
+                                              float(eps_pi), float(eps_phi), _stream_ptr(self.device)))
+
+    def boson_energy(self, phi, pi, U: float):
+        """sum pi^2/2 + phi^2/(2 delta U) in FP64, as a 0-dim device tensor."""
+        self._phi(phi)
+        self._phi(pi)
+        E = torch.empty((), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_boson_energy(self._h, self._p(phi), self._p(pi), float(U), self._p(E),
+                                                 _stream_ptr(self.device)))
+        return E
+
+
 from .autograd import PseudofermionAction  # noqa: E402

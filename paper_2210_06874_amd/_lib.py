@@ -41,6 +41,8 @@ SIGNATURES = {
     "hub_cg_solve": (_P, _P, _P, _P, _I, ctypes.POINTER(HubCgOpts), ctypes.POINTER(HubCgInfo), _P),
     "hub_force": (_P, _P, _P, _P, _I, _P),
     "hub_action": (_P, _P, _P, _I, _P, _P),
+    "hub_md_update": (_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P),
+    "hub_boson_energy": (_P, _P, _P, ctypes.c_double, _P, _P),
     "hub_query": (_P, ctypes.POINTER(_I), ctypes.POINTER(_I)),
     "hub_last_error": (),
 }

@@ -477,6 +477,33 @@ hub_status hub_action(hub_ctx* c, const void* chi, const void* x, int32_t nrhs, 
     return launch_check("k_dot_re");
 }
 
+hub_status hub_md_update(hub_ctx* c, double* phi, double* pi, const double* dSdphi, double U, double eps_pi,
+                         double eps_phi, void* stream) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (!phi || !pi || !dSdphi) return fail(HUB_ERR_ARG, "NULL array argument");
+    if (!(U > 0.0) || !std::isfinite(U) || !std::isfinite(eps_pi) || !std::isfinite(eps_phi))
+        return fail(HUB_ERR_ARG, "U must be > 0 and the step sizes finite");
+    const size_t bytes = (size_t)c->N * sizeof(double);
+    if (overlaps(phi, bytes, pi, bytes) || overlaps(phi, bytes, dSdphi, bytes) || overlaps(pi, bytes, dSdphi, bytes))
+        return fail(HUB_ERR_ARG, "phi, pi and dSdphi must not overlap");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_md_update, dim3(1024), dim3(kThreads), 0, st, phi, pi, dSdphi, c->N, 1.0 / (c->delta * U),
+                       eps_pi, eps_phi);
+    return launch_check("k_md_update");
+}
+
+hub_status hub_boson_energy(hub_ctx* c, const double* phi, const double* pi, double U, double* out_dev,
+                            void* stream) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (!phi || !pi || !out_dev) return fail(HUB_ERR_ARG, "NULL array argument");
+    if (!(U > 0.0) || !std::isfinite(U)) return fail(HUB_ERR_ARG, "U must be > 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    RedArgs ra{c->partials, c->counters + 7, c->Nt, 1};
+    hipLaunchKernelGGL(k_boson_energy, dim3(c->Nt), dim3(kThreads), 0, st, phi, pi, c->V, 1.0 / (c->delta * U),
+                       FinStore{out_dev, 1}, ra);
+    return launch_check("k_boson_energy");
+}
+
 hub_status hub_query(const hub_ctx* c, int32_t* path, int32_t* lds_bytes) {
     if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
     if (path) *path = c->path;

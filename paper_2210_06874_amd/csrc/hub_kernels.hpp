@@ -904,6 +904,36 @@ k_dot_re(const cx<double>* __restrict__ a, const cx<double>* __restrict__ b, int
     reduce_and_finalize(acc, rhs, t, ra, fin, red_lds);
 }
 
+// Molecular-dynamics update of the HMC trajectory: F = phi/(delta U) + dS_f/dphi,
+// pi -= eps_pi F, then phi += eps_phi pi.
+__global__ void __launch_bounds__(kThreads)
+k_md_update(double* __restrict__ phi, double* __restrict__ pi, const double* __restrict__ g, long long n,
+            double inv_dU, double eps_pi, double eps_phi) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double f = fma(phi[i], inv_dU, g[i]);
+        const double p = fma(-eps_pi, f, pi[i]);
+        pi[i] = p;
+        phi[i] = fma(eps_phi, p, phi[i]);
+    }
+}
+
+// Bosonic part of the HMC Hamiltonian, sum over one slice per block:
+// pi^2 / 2 + phi^2 / (2 delta U).
+__global__ void __launch_bounds__(kThreads)
+k_boson_energy(const double* __restrict__ phi, const double* __restrict__ pi, int V, double inv_dU, FinStore fin,
+               RedArgs ra) {
+    __shared__ double red_lds[64];
+    const int t = blockIdx.x;
+    const long long base = (long long)t * V;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < V; i += blockDim.x) {
+        const double a = phi[base + i], b = pi[base + i];
+        acc += 0.5 * b * b + 0.5 * inv_dU * a * a;
+    }
+    reduce_and_finalize(acc, 0, t, ra, fin, red_lds);
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_sum_rhs(const double* __restrict__ parts, double* __restrict__ g, long long n, int nrhs) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;

@@ -1,0 +1,56 @@
+"""Pins of the oracle HMC trajectory: time reversibility, second-order energy error of
+the leapfrog (which also pins the force against the Hamiltonian), and the heat bath."""
+import numpy as np
+
+import oracle as O
+from oracle import hmc as OH
+from workloads import TINY, draw_weak_field, draw_hmc_randoms
+
+
+def _setup():
+    # a well-conditioned starting field (prior draws scaled by delta), where the leapfrog
+    # is in its asymptotic regime at these step sizes
+    w = TINY
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+    phi = draw_weak_field(w)[0]
+    (pi, rho, u), = draw_hmc_randoms(w, 1, seed=3)
+    return w, op, phi, pi, rho, u
+
+
+def test_reversibility():
+    """Integrate forward, flip the momentum, integrate back: the field returns."""
+    w, op, phi, pi, rho, u = _setup()
+    chi = op.apply_M(phi, rho)
+    phi1, pi1, dH, _, _ = OH.trajectory(op, w.U, phi, pi, rho, u, n_md=6, eps=0.05)
+    # backwards with the same chi: a trajectory from (phi1, -pi1) whose heat bath gives chi
+    rho_back = np.linalg.solve(op.dense_M(phi1), chi.ravel()).reshape(rho.shape)
+    phi2, pi2, dH2, _, _ = OH.trajectory(op, w.U, phi1, -pi1, rho_back, u, n_md=6, eps=0.05)
+    np.testing.assert_allclose(phi2, phi, atol=1e-9)
+    np.testing.assert_allclose(-pi2, pi, atol=1e-9)
+    assert abs(dH + dH2) < 1e-9
+
+
+def test_energy_error_is_second_order():
+    """Leapfrog: dH(eps) ~ eps^2 at fixed trajectory length, so halving eps quarters dH.
+    A force that is not the gradient of H breaks this scaling."""
+    w, op, phi, pi, rho, u = _setup()
+    dh = []
+    for n, eps in ((16, 0.05), (32, 0.025), (64, 0.0125)):
+        dh.append(abs(OH.trajectory(op, w.U, phi, pi, rho, u, n_md=n, eps=eps)[2]))
+    r1, r2 = dh[0] / dh[1], dh[1] / dh[2]
+    assert 3.3 < r1 < 4.7 and 3.6 < r2 < 4.4, (dh, r1, r2)
+
+
+def test_heat_bath_initial_action():
+    """Sec. 2: chi = M rho gives chi^dag (M M^dag)^{-1} chi = rho^dag rho."""
+    w, op, phi, pi, rho, u = _setup()
+    chi = op.apply_M(phi, rho)
+    x = O.dense_solve(op, phi, chi)
+    assert abs(O.action(chi, x) - np.vdot(rho, rho).real) < 1e-9 * np.vdot(rho, rho).real
+
+
+def test_metropolis_decision():
+    w, op, phi, pi, rho, u = _setup()
+    phi1, pi1, dH, acc, out = OH.trajectory(op, w.U, phi, pi, rho, u, n_md=4, eps=0.1)
+    assert acc == (dH <= 0 or u < np.exp(-dH))
+    np.testing.assert_array_equal(out, phi1 if acc else phi)

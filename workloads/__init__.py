@@ -106,3 +106,17 @@ def pick_entries(w: Lattice, count: int = 64, seed: int = 0) -> np.ndarray:
     """`count` distinct (t, x) field entries, as flat indices into [Nt, V]."""
     rng = np.random.default_rng(seed)
     return rng.choice(w.N, size=min(count, w.N), replace=False)
+
+
+def draw_hmc_randoms(w: Lattice, n_traj: int, seed: int = 0, nrhs: int = 1):
+    """Random numbers of n_traj HMC trajectories (Sec. 2): momenta pi ~ e^{-pi^2/2}
+    (float64 [Nt, V]), heat-bath vectors rho ~ e^{-rho^dag rho} (complex128 [nrhs, Nt, V])
+    and the Metropolis uniform u in [0, 1), in that order per trajectory."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_traj):
+        pi = rng.normal(0.0, 1.0, size=(w.Nt, w.V))
+        rho = draw_complex(w, nrhs=nrhs, rng=rng)
+        u = float(rng.random())
+        out.append((pi, rho, u))
+    return out
