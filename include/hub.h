@@ -7,7 +7,9 @@
  * conjugate gradients, and computes the pseudofermion force dS/dphi of
  * S = chi^dag (M M^dag)^{-1} chi (Sec. 2, eq. "hamiltonian").
  *
- * Operator (all indices mod Nt, E = exp(delta*kappa*K), delta = beta/Nt):
+ * Operator (all indices mod Nt, E = e^{delta mu} exp(delta*kappa*K), delta = beta/Nt; the
+ * chemical potential mu is 0 at half filling, and the weight of Sec. 3 away from it is
+ * det(M[phi,mu] M[phi,-mu]^dag)):
  *     (M v)_t     = v_t - B_t     E (e^{i phi_{t-1}} * v_{t-1})
  *     (M^dag v)_t = v_t - B_{t+1} e^{-i phi_t} * (E v_{t+1})
  * with B_0 = -1 (antiperiodic wrap) and B_t = +1 otherwise.  K is the
@@ -72,6 +74,7 @@ typedef struct {
     double kappa;       /* hopping amplitude                                                    */
     int32_t nrhs_max;   /* largest nrhs any call on this context will pass, >= 1                */
     int32_t path;       /* hub_path                                                              */
+    double mu;          /* chemical potential: every time hop carries e^{delta mu} (0 = half filling) */
 } hub_params;
 
 typedef struct {

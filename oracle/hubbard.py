@@ -30,6 +30,9 @@ Conventions (readings where the paper is silent):
 * (M v)_t = v_t - B_t * E * D_{t-1} v_{t-1},  B_0 = -1, B_t = +1 otherwise,
   E = exp(delta*kappa*K), D_t = diag(e^{i phi_t}), time indices mod Nt.
 * (M^dag v)_t = v_t - B_{t+1} * D_t^* E v_{t+1}.
+* away from half filling (Sec. 3) the chemical potential mu multiplies every time hop
+  by e^{delta mu}: E = e^{delta mu} exp(delta*kappa*K); the weight is
+  det(M[phi,mu] M[phi,-mu]^dag).
 
 Functions carrying no independent pin say "parity unpinned" in their docstring;
 all others are pinned by the tests in tests/test_oracle_pins.py.
@@ -113,8 +116,10 @@ class HubbardOperator:
                     usable at every size.
     """
 
-    def __init__(self, L: int, Nt: int, beta: float, kappa: float = 1.0, mode: str | None = None):
+    def __init__(self, L: int, Nt: int, beta: float, kappa: float = 1.0, mode: str | None = None,
+                 mu: float = 0.0):
         self.L, self.Nt, self.beta, self.kappa = L, Nt, float(beta), float(kappa)
+        self.mu = float(mu)
         self.V = 2 * L * L
         self.N = self.V * Nt
         self.delta = self.beta / Nt
@@ -123,8 +128,10 @@ class HubbardOperator:
             mode = "dense-E" if self.V <= 6000 else "expm"
         self.mode = mode
         self.B = antiperiodic_signs(Nt)
+        # the chemical potential multiplies every time hop by e^{delta mu}
+        self.fmu = math.exp(self.delta * self.mu)
         if mode == "dense-E":
-            self.E = hopping_exponential(L, self.dk)
+            self.E = self.fmu * hopping_exponential(L, self.dk)
         elif mode == "expm":
             self.E = None
             self.Ks = (self.dk * hopping_matrix_sparse(L)).tocsc()
@@ -139,7 +146,7 @@ class HubbardOperator:
         if self.mode == "dense-E":
             out = self.E @ cols
         else:
-            out = spla.expm_multiply(self.Ks, cols)
+            out = self.fmu * spla.expm_multiply(self.Ks, cols)
         m = flat.shape[0]
         res = (out[:, :m] + 1j * out[:, m:]).T
         return res.reshape(shp)

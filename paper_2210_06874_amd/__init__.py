@@ -45,13 +45,14 @@ class Hubbard:
     """One lattice: L x L honeycomb torus (V = 2 L^2 sites), Nt slices, beta, kappa."""
 
     def __init__(self, L: int, Nt: int, beta: float, kappa: float = 1.0, nrhs_max: int = 1,
-                 path: str = "auto", device=None):
+                 path: str = "auto", device=None, mu: float = 0.0):
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.L, self.Nt, self.beta, self.kappa, self.nrhs_max = L, Nt, float(beta), float(kappa), nrhs_max
+        self.mu = float(mu)
         self.V = 2 * L * L
         self.N = self.V * Nt
-        prm = _lib.HubParams(L, Nt, float(beta), float(kappa), nrhs_max, _PATH[path])
+        prm = _lib.HubParams(L, Nt, float(beta), float(kappa), nrhs_max, _PATH[path], float(mu))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self.lib.hub_create(ctypes.byref(prm), _stream_ptr(self.device), ctypes.byref(h)))

@@ -16,7 +16,8 @@ HUB_PATH_AUTO, HUB_PATH_FUSED, HUB_PATH_SPLIT = 0, 1, 2
 
 class HubParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("Nt", ctypes.c_int32), ("beta", ctypes.c_double),
-                ("kappa", ctypes.c_double), ("nrhs_max", ctypes.c_int32), ("path", ctypes.c_int32)]
+                ("kappa", ctypes.c_double), ("nrhs_max", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("mu", ctypes.c_double)]
 
 
 class HubCgOpts(ctypes.Structure):

@@ -337,8 +337,8 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     if (prm->L < 1 || prm->L > 1024) return fail(HUB_ERR_ARG, "L=%d outside [1, 1024]", prm->L);
     if (prm->Nt < 1) return fail(HUB_ERR_ARG, "Nt=%d < 1", prm->Nt);
     if (prm->nrhs_max < 1) return fail(HUB_ERR_ARG, "nrhs_max=%d < 1", prm->nrhs_max);
-    if (!std::isfinite(prm->beta) || !std::isfinite(prm->kappa))
-        return fail(HUB_ERR_ARG, "beta and kappa must be finite");
+    if (!std::isfinite(prm->beta) || !std::isfinite(prm->kappa) || !std::isfinite(prm->mu))
+        return fail(HUB_ERR_ARG, "beta, kappa and mu must be finite");
     if (prm->path < HUB_PATH_AUTO || prm->path > HUB_PATH_SPLIT) return fail(HUB_ERR_ARG, "bad path %d", prm->path);
     FftPlan plan{};
     if (!make_plan(prm->L, &plan))
@@ -373,7 +373,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
                                                                                       : HUB_PATH_FUSED;
 
     std::vector<double> roots, etab;
-    build_tables(plan, c->delta * c->kappa, roots, etab);
+    build_tables(plan, c->delta * c->kappa, c->delta * prm->mu, roots, etab);
     std::vector<float> roots32(roots.begin(), roots.end()), etab32(etab.begin(), etab.end());
     hipStream_t st = static_cast<hipStream_t>(stream);
 #define CREATE_OR_BAIL(expr)                                                                   \

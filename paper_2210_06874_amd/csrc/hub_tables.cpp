@@ -6,6 +6,8 @@
 // K(k) = [[0, f(k)], [conj f(k), 0]], f(k) = 1 + e^{-i k1} + e^{-i k2}, whose
 // eigenvalues +-|f(k)| are the two free bands of Sec. 1.  Because K(k)^2 = |f|^2,
 //     exp(dk K(k)) = cosh(dk|f|) 1 + sinh(dk|f|)/|f| K(k).
+// A chemical potential mu multiplies every time hop by e^{delta mu} (Sec. 1 Hamiltonian:
+// mu couples to the charge; Sec. 3 weight det(M[phi,mu] M[phi,-mu]^dag)).
 #include <cmath>
 
 #include "hub_tables.hpp"
@@ -48,7 +50,7 @@ int digit_reversed_position(const FftPlan& plan, int k) {
     return pos;
 }
 
-void build_tables(const FftPlan& plan, double dk, std::vector<double>& roots,
+void build_tables(const FftPlan& plan, double dk, double dmu, std::vector<double>& roots,
                   std::vector<double>& etab) {
     const int L = plan.L;
     const double two_pi = 6.283185307179586476925286766559;
@@ -61,7 +63,7 @@ void build_tables(const FftPlan& plan, double dk, std::vector<double>& roots,
     std::vector<int> inv_pos(L);
     for (int k = 0; k < L; ++k) inv_pos[digit_reversed_position(plan, k)] = k;
     etab.assign(4 * (size_t)L * L, 0.0);
-    const double norm = 1.0 / ((double)L * (double)L);
+    const double norm = std::exp(dmu) / ((double)L * (double)L);
     for (int p1 = 0; p1 < L; ++p1) {
         const int k1 = inv_pos[p1];
         for (int p2 = 0; p2 < L; ++p2) {

@@ -26,8 +26,9 @@ int digit_reversed_position(const FftPlan& plan, int k);
 //   roots[m]   = e^{-2 pi i m / L}, m = 0..L-1, angles from the integer m (exact), as (re, im)
 //   etab[p]    = (c, Re sf, Im sf, 0) / L^2 at transform position p = p1*L + p2, where
 //                k = (k1, k2) is the momentum stored at p, f = 1 + e^{-i k1} + e^{-i k2},
-//                c = cosh(dk |f|), s = sinh(dk |f|)/|f| (-> dk at |f| = 0), sf = s*f.
-void build_tables(const FftPlan& plan, double delta_kappa, std::vector<double>& roots,
+//                c = cosh(dk |f|), s = sinh(dk |f|)/|f| (-> dk at |f| = 0), sf = s*f,
+//                all times e^{delta mu}.
+void build_tables(const FftPlan& plan, double delta_kappa, double delta_mu, std::vector<double>& roots,
                   std::vector<double>& etab);
 
 }  // namespace hub

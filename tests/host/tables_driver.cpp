@@ -7,9 +7,10 @@
 #include "hub_tables.hpp"
 
 int main(int argc, char** argv) {
-    if (argc != 3) return 2;
+    if (argc != 3 && argc != 4) return 2;
     const int L = std::atoi(argv[1]);
     const double dk = std::atof(argv[2]);
+    const double dmu = argc == 4 ? std::atof(argv[3]) : 0.0;
     hub::FftPlan plan{};
     if (!hub::make_plan(L, &plan)) {
         std::printf("noplan\n");
@@ -22,7 +23,7 @@ int main(int argc, char** argv) {
     for (int k = 0; k < L; ++k) std::printf(" %d", hub::digit_reversed_position(plan, k));
     std::printf("\n");
     std::vector<double> roots, etab;
-    hub::build_tables(plan, dk, roots, etab);
+    hub::build_tables(plan, dk, dmu, roots, etab);
     for (int m = 0; m < L; ++m) std::printf("root %.17g %.17g\n", roots[2 * m], roots[2 * m + 1]);
     for (int p = 0; p < L * L; ++p)
         std::printf("e %.17g %.17g %.17g\n", etab[4 * p], etab[4 * p + 1], etab[4 * p + 2]);

@@ -54,13 +54,13 @@ def test_argument_errors_before_any_device_call():
     assert lib.hub_create(None, None, ctypes.byref(h)) == L.HUB_ERR_ARG
     assert b"NULL" in lib.hub_last_error()
     for bad in [dict(L=0), dict(L=19), dict(L=2048), dict(Nt=0), dict(nrhs_max=0), dict(path=7),
-                dict(beta=float("nan"))]:
-        prm = dict(L=3, Nt=8, beta=2.0, kappa=1.0, nrhs_max=1, path=0)
+                dict(beta=float("nan")), dict(mu=float("inf"))]:
+        prm = dict(L=3, Nt=8, beta=2.0, kappa=1.0, nrhs_max=1, path=0, mu=0.0)
         prm.update(bad)
-        p = L.HubParams(prm["L"], prm["Nt"], prm["beta"], prm["kappa"], prm["nrhs_max"], prm["path"])
+        p = L.HubParams(prm["L"], prm["Nt"], prm["beta"], prm["kappa"], prm["nrhs_max"], prm["path"], prm["mu"])
         assert lib.hub_create(ctypes.byref(p), None, ctypes.byref(h)) == L.HUB_ERR_ARG, bad
         assert h.value is None
-    assert lib.hub_create(ctypes.byref(L.HubParams(3, 8, 2.0, 1.0, 1, 0)), None, None) == L.HUB_ERR_ARG
+    assert lib.hub_create(ctypes.byref(L.HubParams(3, 8, 2.0, 1.0, 1, 0, 0.0)), None, None) == L.HUB_ERR_ARG
     x = ctypes.c_void_p(1)
     assert lib.hub_apply_M(None, x, x, x, 1, None) == L.HUB_ERR_ARG
     assert lib.hub_apply_Mdag(None, x, x, x, 1, None) == L.HUB_ERR_ARG
@@ -73,12 +73,13 @@ def test_argument_errors_before_any_device_call():
 
 
 # ----------------------------------------------------------------------------- host tables
-def _tables(tmp_path, L, dk):
+def _tables(tmp_path, L, dk, dmu=0.0):
     exe = tmp_path / "tables"
     if not exe.exists():
         subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, os.path.join(ROOT, "tests", "host", "tables_driver.cpp"),
                         os.path.join(CSRC, "hub_tables.cpp"), "-o", str(exe)], check=True)
-    out = subprocess.run([str(exe), str(L), repr(dk)], capture_output=True, text=True, check=True).stdout
+    out = subprocess.run([str(exe), str(L), repr(dk), repr(dmu)], capture_output=True, text=True,
+                         check=True).stdout
     lines = out.splitlines()
     if lines[0] == "noplan":
         return None
@@ -119,17 +120,18 @@ def test_plan_positions_follow_the_transform(tmp_path, L):
     np.testing.assert_allclose(roots, np.exp(-2j * np.pi * np.arange(L) / L), atol=2e-16)
 
 
-@pytest.mark.parametrize("L,dk", [(3, 0.25), (12, 0.125), (51, 0.0625), (6, 1.5)])
-def test_momentum_hopping_table_is_the_2x2_exponential(tmp_path, L, dk):
-    """E(k)/L^2 at every transform position equals scipy's expm of dk [[0, f], [conj f, 0]]."""
-    plan, pos, _, etab = _tables(tmp_path, L, dk)
+@pytest.mark.parametrize("L,dk,dmu", [(3, 0.25, 0.0), (12, 0.125, 0.0), (51, 0.0625, 0.0), (6, 1.5, 0.0),
+                                      (6, 0.25, 0.1), (12, 0.125, -0.05)])
+def test_momentum_hopping_table_is_the_2x2_exponential(tmp_path, L, dk, dmu):
+    """E(k)/L^2 at every transform position equals scipy's expm of dk [[0, f], [conj f, 0]] + dmu."""
+    plan, pos, _, etab = _tables(tmp_path, L, dk, dmu)
     inv = np.empty(L, dtype=int)
     inv[pos] = np.arange(L)
     for p1 in range(L):
         for p2 in range(L):
             k1, k2 = 2 * np.pi * inv[p1] / L, 2 * np.pi * inv[p2] / L
             f = 1 + np.exp(-1j * k1) + np.exp(-1j * k2)
-            E = scipy.linalg.expm(dk * np.array([[0, f], [np.conj(f), 0]]))
+            E = scipy.linalg.expm(dk * np.array([[0, f], [np.conj(f), 0]]) + dmu * np.eye(2))
             c, sr, si = etab[p1 * L + p2] * L * L
             np.testing.assert_allclose([c, sr + 1j * si], [E[0, 0].real, E[0, 1]], atol=5e-15)
             np.testing.assert_allclose(E[1, 0], sr - 1j * si, atol=5e-15)

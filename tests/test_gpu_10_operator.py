@@ -185,3 +185,17 @@ def test_half_and_whole_slice_kernels_agree(prec):
     for r in range(2):
         assert_close_elementwise(one[r][0], ref[r], tol, f"half-slice kernel rhs {r}")
         assert_close_elementwise(two[r], ref[r], tol, f"whole-slice kernel rhs {r}")
+
+
+@pytest.mark.parametrize("mu", [0.35, -0.6])
+def test_apply_with_chemical_potential(mu):
+    """mu != 0 (Sec. 3): every time hop carries e^{delta mu}; fused and L = 51 kernels."""
+    from paper_2210_06874_amd import Hubbard
+    for w in (SMALL, PREC):
+        print(f"[case] apply mu={mu} {w.name}", flush=True)
+        phi, v = draw_inputs(w, seed=19)
+        hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, mu=mu)
+        op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa, mode="expm", mu=mu)
+        assert_close_elementwise(to_np(hub.apply_M(to_dev(phi), to_dev(v))), op.apply_M(phi, v), RTOL64, "M")
+        assert_close_elementwise(to_np(hub.apply_Mdag(to_dev(phi), to_dev(v))), op.apply_Mdag(phi, v), RTOL64,
+                                 "Mdag")

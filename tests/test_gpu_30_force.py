@@ -90,3 +90,21 @@ def test_force_gauge_sum_rule_precision_workload():
     rhs = -2 * np.einsum("rtx,rtx->t", np.conj(c), x).imag
     scale = np.abs(g).sum(axis=1).max()
     np.testing.assert_allclose(lhs, rhs, atol=1e-9 * scale)
+
+
+def test_cg_and_force_with_chemical_potential():
+    """M[phi, mu] M[phi, mu]^dag stays Hermitian positive definite: CG and force at mu != 0
+    against the oracle."""
+    from paper_2210_06874_amd import Hubbard
+    w = TINY
+    mu = 0.4
+    phi, chi = draw_inputs(w)
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa, mu=mu)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, mu=mu)
+    res = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-12, max_iter=20000)
+    x = to_np(res.x)
+    assert np.linalg.norm(chi - op.apply_A(phi, x)) <= 2e-12 * np.linalg.norm(chi)
+    g = to_np(hub.force(to_dev(phi), res.x))
+    assert_close_elementwise(g, O.force(op, phi, x), 1e-12, "force")
+    gd = O.force_dense(op, phi, O.dense_solve(op, phi, chi))
+    assert np.linalg.norm(g - gd) <= 1e-7 * np.linalg.norm(gd)

@@ -378,3 +378,46 @@ def test_degenerate_sizes():
         M = op.dense_M(phi)
         np.testing.assert_allclose(op.apply_M(phi, v).ravel(), M @ v.ravel(), atol=1e-13)
         np.testing.assert_allclose(op.apply_Mdag(phi, u).ravel(), M.conj().T @ u.ravel(), atol=1e-13)
+
+
+# ----------------------------------------------------------------------------- chemical potential
+@pytest.mark.parametrize("mu", [0.3, -0.7])
+def test_free_log_det_with_chemical_potential(mu):
+    """phi = 0: det M[0, mu] = prod_{k,+-} (1 + e^{beta (mu +- kappa |f(k)|)}) (free fermions
+    in the grand-canonical ensemble; Sec. 1 Hamiltonian with mu)."""
+    L, Nt, beta = 3, 8, 2.0
+    op = O.HubbardOperator(L, Nt, beta, mu=mu)
+    _, ld = np.linalg.slogdet(op.dense_M(np.zeros((Nt, 2 * L * L))))
+    a = np.abs(CF.f_of_k(L)).ravel()
+    ref = np.sum(np.log1p(np.exp(beta * (mu + a)))) + np.sum(np.log1p(np.exp(beta * (mu - a))))
+    assert abs(ld - ref) < 1e-11 * abs(ref)
+
+
+def test_weight_away_from_half_filling_is_not_positive():
+    """Sec. 3: det(M[phi,mu] M[phi,-mu]^dag) is real and positive at mu = 0 but complex for
+    mu != 0 (the sign problem); at phi = 0 it stays positive."""
+    w = TINY
+    phi, _ = draw_inputs(w)
+    for mu, complex_expected in ((0.0, False), (0.4, True)):
+        Mp = O.HubbardOperator(w.L, w.Nt, w.beta, mu=mu).dense_M(phi)
+        Mm = O.HubbardOperator(w.L, w.Nt, w.beta, mu=-mu).dense_M(phi)
+        sign, _ = np.linalg.slogdet(Mp @ Mm.conj().T)
+        assert (abs(np.angle(sign)) > 1e-6) == complex_expected, (mu, sign)
+        Mp0 = O.HubbardOperator(w.L, w.Nt, w.beta, mu=mu).dense_M(np.zeros_like(phi))
+        Mm0 = O.HubbardOperator(w.L, w.Nt, w.beta, mu=-mu).dense_M(np.zeros_like(phi))
+        s0, _ = np.linalg.slogdet(Mp0 @ Mm0.conj().T)
+        assert abs(s0 - 1) < 1e-10
+
+
+def test_chemical_potential_routes_agree():
+    """e^{delta mu} on the Krylov-exp route equals the dense route; adjointness holds."""
+    w = TINY
+    phi, v = draw_inputs(w, seed=8)
+    u = draw_complex(w, seed=9)
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, mu=0.5)
+    ope = O.HubbardOperator(w.L, w.Nt, w.beta, mu=0.5, mode="expm")
+    np.testing.assert_allclose(ope.apply_M(phi, v), op.apply_M(phi, v), atol=1e-13)
+    np.testing.assert_allclose(op.dense_M(phi) @ v.ravel(), op.apply_M(phi, v).ravel(), atol=1e-13)
+    a = np.vdot(u, op.apply_M(phi, v))
+    b = np.vdot(op.apply_Mdag(phi, u), v)
+    assert abs(a - b) < 1e-12 * abs(a)
