@@ -47,8 +47,9 @@ import scipy.sparse.linalg as spla
 
 __all__ = [
     "site_index", "honeycomb_bonds", "hopping_matrix", "hopping_matrix_sparse",
-    "hopping_exponential", "antiperiodic_signs", "HubbardOperator", "cg_solve",
-    "dense_solve", "action", "force", "force_dense",
+    "hopping_exponential", "antiperiodic_signs", "HubbardOperator", "LinearHubbardOperator",
+    "cg_solve", "dense_solve", "action", "force", "force_dense", "force_linear",
+    "force_dense_linear", "dense_solve_op",
 ]
 
 
@@ -285,3 +286,132 @@ def force_dense(op: HubbardOperator, phi: np.ndarray, x: np.ndarray) -> np.ndarr
             g[c] = -tot
             dM[tn * V:(tn + 1) * V, c] = 0.0
     return g.reshape(Nt, V)
+
+
+# --------------------------------------------------------------------------- linear form
+class LinearHubbardOperator:
+    """The fermion matrix exactly as printed in eq. "ferm_op" (Sec. 2), linear in delta*kappa:
+
+        M^AA_{(x,t)(y,t')} = delta_xy (delta_{t+1,t'} - delta_{tt'} e^{i phi_{x,t}})
+        M^BB_{(x,t)(y,t')} = delta_xy (delta_{tt'} - delta_{t-1,t'} e^{-i phi_{x,t}})
+        M^AB = M^BA      = -delta kappa delta_<x,y> delta_{tt'}
+
+    with phi = delta * the paper's field (so e^{i delta phi_paper} = e^{i phi}) and
+    antiperiodic time: a hop across the wrap carries -1 (B_t below).
+    """
+
+    def __init__(self, L: int, Nt: int, beta: float, kappa: float = 1.0):
+        self.L, self.Nt, self.beta, self.kappa = L, Nt, float(beta), float(kappa)
+        self.V = 2 * L * L
+        self.N = self.V * Nt
+        self.delta = self.beta / Nt
+        self.dk = self.delta * self.kappa
+        self.nA = L * L
+        self.B = antiperiodic_signs(Nt)
+        self.K = hopping_matrix_sparse(L).tocsr()
+
+    def _shape(self, v):
+        v = np.asarray(v, dtype=np.complex128)
+        return v.reshape(-1, self.Nt, self.V), v.shape
+
+    def _hop(self, vv):
+        flat = vv.reshape(-1, self.V)
+        return (self.K @ flat.T).T.reshape(vv.shape)
+
+    def apply_M(self, phi, v):
+        vv, shp = self._shape(v)
+        A, Bs = slice(0, self.nA), slice(self.nA, self.V)
+        Bn = np.roll(self.B, -1)[None, :, None]                     # B_{t+1}
+        nxt = Bn * np.roll(vv, -1, axis=1)                          # v_{t+1} across the wrap
+        prv = self.B[None, :, None] * np.roll(vv, 1, axis=1)       # v_{t-1} across the wrap
+        out = np.empty_like(vv)
+        out[..., A] = nxt[..., A] - np.exp(1j * phi[:, A])[None] * vv[..., A]
+        out[..., Bs] = vv[..., Bs] - np.exp(-1j * phi[:, Bs])[None] * prv[..., Bs]
+        out -= self.dk * self._hop(vv)
+        return out.reshape(shp)
+
+    def apply_Mdag(self, phi, v):
+        vv, shp = self._shape(v)
+        A, Bs = slice(0, self.nA), slice(self.nA, self.V)
+        Bn = np.roll(self.B, -1)[None, :, None]
+        prv = self.B[None, :, None] * np.roll(vv, 1, axis=1)       # B_t v_{t-1}
+        nxt = Bn * np.roll(vv, -1, axis=1)                          # B_{t+1} v_{t+1}
+        ph_next = np.roll(phi, -1, axis=0)                          # phi_{t+1}
+        out = np.empty_like(vv)
+        out[..., A] = prv[..., A] - np.exp(-1j * phi[:, A])[None] * vv[..., A]
+        out[..., Bs] = vv[..., Bs] - np.exp(1j * ph_next[:, Bs])[None] * nxt[..., Bs]
+        out -= self.dk * self._hop(vv)
+        return out.reshape(shp)
+
+    def apply_A(self, phi, v):
+        return self.apply_M(phi, self.apply_Mdag(phi, v))
+
+    def dense_M(self, phi):
+        """Entry by entry from eq. "ferm_op" (tiny lattices)."""
+        V, Nt, nA = self.V, self.Nt, self.nA
+        M = np.zeros((self.N, self.N), dtype=np.complex128)
+        K = self.K.toarray()
+        for t in range(Nt):
+            for x in range(V):
+                r = t * V + x
+                if x < nA:
+                    tn = (t + 1) % Nt
+                    M[r, tn * V + x] += self.B[tn]
+                    M[r, r] -= np.exp(1j * phi[t, x])
+                else:
+                    tp = (t - 1) % Nt
+                    M[r, r] += 1.0
+                    M[r, tp * V + x] -= self.B[t] * np.exp(-1j * phi[t, x])
+            M[t * V:(t + 1) * V, t * V:(t + 1) * V] -= self.dk * K
+        return M
+
+    def dense_dM(self, phi, t, x):
+        """d M / d phi_{t,x} as a dense matrix (one nonzero entry)."""
+        dM = np.zeros((self.N, self.N), dtype=np.complex128)
+        V = self.V
+        if x < self.nA:
+            dM[t * V + x, t * V + x] = -1j * np.exp(1j * phi[t, x])
+        else:
+            tp = (t - 1) % self.Nt
+            dM[t * V + x, tp * V + x] = 1j * self.B[t] * np.exp(-1j * phi[t, x])
+        return dM
+
+
+def force_linear(op: LinearHubbardOperator, phi, x) -> np.ndarray:
+    """dS/dphi for the linear form, -2 Re(x^dag dM y) with y = M^dag x, summed over rhs.
+
+    phi_{t,z} enters one entry of M: the diagonal -e^{i phi} on A sites, the entry
+    -B_t e^{-i phi} coupling slice t-1 on B sites.
+    """
+    xx = np.asarray(x, dtype=np.complex128).reshape(-1, op.Nt, op.V)
+    g = np.zeros((op.Nt, op.V))
+    A, Bs = slice(0, op.nA), slice(op.nA, op.V)
+    for xr in xx:
+        y = op.apply_Mdag(phi, xr)
+        yprev = np.roll(y, 1, axis=0)                               # y_{t-1} (unsigned)
+        gA = -2.0 * (np.exp(1j * phi[:, A]) * np.conj(xr[:, A]) * y[:, A]).imag
+        gB = 2.0 * op.B[:, None] * (np.exp(-1j * phi[:, Bs]) * np.conj(xr[:, Bs]) * yprev[:, Bs]).imag
+        g[:, A] += gA
+        g[:, Bs] += gB
+    return g
+
+
+def force_dense_linear(op: LinearHubbardOperator, phi, x) -> np.ndarray:
+    """-x^dag (dM M^dag + M dM^dag) x from dense derivatives (tiny lattices)."""
+    M = op.dense_M(phi)
+    xx = np.asarray(x, dtype=np.complex128).reshape(-1, op.N)
+    g = np.zeros(op.N)
+    for t in range(op.Nt):
+        for z in range(op.V):
+            dM = op.dense_dM(phi, t, z)
+            dA = dM @ M.conj().T + M @ dM.conj().T
+            g[t * op.V + z] = -sum(np.vdot(xr, dA @ xr).real for xr in xx)
+    return g.reshape(op.Nt, op.V)
+
+
+def dense_solve_op(op, phi, chi):
+    """x = (M M^dag)^{-1} chi by a dense solve, for any operator with dense_M."""
+    M = op.dense_M(phi)
+    A = M @ M.conj().T
+    chi = np.asarray(chi, dtype=np.complex128).reshape(-1, op.N)
+    return np.linalg.solve(A, chi.T).T.reshape(-1, op.Nt, op.V)
