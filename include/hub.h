@@ -7,7 +7,9 @@
  * conjugate gradients, and computes the pseudofermion force dS/dphi of
  * S = chi^dag (M M^dag)^{-1} chi (Sec. 2, eq. "hamiltonian").
  *
- * Operator (all indices mod Nt, E = e^{delta mu} exp(delta*kappa*K), delta = beta/Nt; the
+ * Two forms of the operator are available (hub_params.form).  HUB_FORM_EXP, the default:
+ * the exponential transfer-matrix form.  Operator (all indices mod Nt,
+ * E = e^{delta mu} exp(delta*kappa*K), delta = beta/Nt; the
  * chemical potential mu is 0 at half filling, and the weight of Sec. 3 away from it is
  * det(M[phi,mu] M[phi,-mu]^dag)):
  *     (M v)_t     = v_t - B_t     E (e^{i phi_{t-1}} * v_{t-1})
@@ -15,6 +17,12 @@
  * with B_0 = -1 (antiperiodic wrap) and B_t = +1 otherwise.  K is the
  * nearest-neighbour hopping matrix of the L x L honeycomb torus (Sec. 1,
  * fig. "honeycomb_lattice"): A(n) is bonded to B(n), B(n-e1), B(n-e2).
+ *
+ * HUB_FORM_LINEAR: eq. "ferm_op" exactly as printed, linear in delta*kappa (mu must be 0):
+ *     A sites: (M v)_{t,x} = B_{t+1} v_{t+1,x} - e^{i phi_{t,x}} v_{t,x}   - dk (K v_t)_x
+ *     B sites: (M v)_{t,x} = v_{t,x} - B_t e^{-i phi_{t,x}} v_{t-1,x}       - dk (K v_t)_x
+ * with dk = delta*kappa; M^dag is its conjugate transpose.  Every entry point below
+ * works for both forms; the solver, the action and the HMC updates are form-independent.
  *
  * Layouts (C-contiguous, fastest index last):
  *     site x = s*L*L + n1*L + n2      (s = 0 for sublattice A, 1 for B)
@@ -67,14 +75,18 @@ typedef enum { HUB_PREC_FP64 = 0, HUB_PREC_MIXED = 1 } hub_prec;
  * SPLIT force one (FUSED fails with HUB_ERR_ARG when the slice does not fit). */
 typedef enum { HUB_PATH_AUTO = 0, HUB_PATH_FUSED = 1, HUB_PATH_SPLIT = 2 } hub_path;
 
+/* Which fermion matrix the context applies (see the top of this file). */
+typedef enum { HUB_FORM_EXP = 0, HUB_FORM_LINEAR = 1 } hub_form;
+
 typedef struct {
-    int32_t L;          /* torus extent, 1 <= L <= 1024; every prime factor of L must be <= 17 */
+    int32_t L;          /* torus extent, 1 <= L <= 1024; HUB_FORM_EXP: every prime factor <= 17   */
     int32_t Nt;         /* time slices, Nt >= 1                                                 */
     double beta;        /* inverse temperature, delta = beta/Nt                                 */
     double kappa;       /* hopping amplitude                                                    */
     int32_t nrhs_max;   /* largest nrhs any call on this context will pass, >= 1                */
     int32_t path;       /* hub_path                                                              */
     double mu;          /* chemical potential: every time hop carries e^{delta mu} (0 = half filling) */
+    int32_t form;       /* hub_form; HUB_FORM_LINEAR ignores `path` and requires mu == 0       */
 } hub_params;
 
 typedef struct {
@@ -92,15 +104,15 @@ typedef struct {
     double recursive_rel_res;   /* the iterated residual's ||r|| / ||chi|| at exit            */
 } hub_cg_info;
 
-/* Create a context on the current HIP device: builds the momentum-space hopping
- * table E(k) (Sec. 1: bands +-kappa|f(k)|) and the DFT roots of unity in FP64.
+/* Create a context on the current HIP device: for HUB_FORM_EXP builds the momentum-space
+ * hopping table E(k) (Sec. 1: bands +-kappa|f(k)|) and the DFT roots of unity in FP64.
  * `stream` is used for the table uploads.  *out is set to NULL on failure. */
 hub_status hub_create(const hub_params* params, void* stream, hub_ctx** out);
 
 /* Release every device allocation of the context (synchronises the device).  NULL is a no-op. */
 void hub_destroy(hub_ctx* ctx);
 
-/* out = M[phi] in  (Sec. 2, eq. "ferm_op", exponential form), FP64.
+/* out = M[phi] in  (Sec. 2, eq. "ferm_op", in the context's form), FP64.
  * in and out: complex128 [nrhs][Nt][V]; must not overlap.  1 <= nrhs <= nrhs_max. */
 hub_status hub_apply_M(hub_ctx* ctx, const double* phi, const void* in, void* out,
                        int32_t nrhs, void* stream);
@@ -130,8 +142,11 @@ hub_status hub_cg_solve(hub_ctx* ctx, const double* phi, const void* chi, void* 
                         const hub_cg_opts* opts, hub_cg_info* info_host, void* stream);
 
 /* dS/dphi of the pseudofermion action S = sum_r chi_r^dag x_r, x_r = (M M^dag)^{-1} chi_r,
- * from the solutions x (complex128 [nrhs][Nt][V]):
+ * from the solutions x (complex128 [nrhs][Nt][V]).  HUB_FORM_EXP:
  *     dSdphi[t][z] = sum_r -2 B_{t+1} Im( e^{i phi_{t,z}} x_{r,t,z} conj((E x_{r,t+1})_z) ).
+ * HUB_FORM_LINEAR, with y_r = M^dag x_r:
+ *     A sites: dSdphi[t][z] = sum_r -2 Im( e^{i phi_{t,z}} conj(x_{r,t,z}) y_{r,t,z} )
+ *     B sites: dSdphi[t][z] = sum_r 2 B_t Im( e^{-i phi_{t,z}} conj(x_{r,t,z}) y_{r,t-1,z} ).
  * dSdphi (double [Nt][V]) is overwritten.  The Gaussian term phi/(delta U) is the caller's. */
 hub_status hub_force(hub_ctx* ctx, const double* phi, const void* x, double* dSdphi,
                      int32_t nrhs, void* stream);
@@ -156,7 +171,8 @@ hub_status hub_boson_energy(hub_ctx* ctx, const double* phi, const double* pi, d
                             void* stream);
 
 /* Report the kernel path the context uses (hub_path value, never AUTO) and the
- * LDS bytes per workgroup of its operator kernel. */
+ * LDS bytes per workgroup of its operator kernel (HUB_FORM_LINEAR: FUSED and 0, one
+ * stencil kernel that uses no dynamic LDS). */
 hub_status hub_query(const hub_ctx* ctx, int32_t* path, int32_t* lds_bytes);
 
 /* Thread-local description of the last non-OK status returned on this thread. */

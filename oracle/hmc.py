@@ -5,7 +5,9 @@ Hamiltonian (eq. "hamiltonian", with phi = delta * the paper's field):
 The trajectory draws nothing itself: the momenta pi0, the heat-bath vector rho
 (chi = M rho) and the Metropolis uniform u are inputs.  Molecular dynamics is the
 leapfrog (half momentum step, alternating full steps, half momentum step); the
-trajectory is accepted with probability min(1, e^{-dH}).
+trajectory is accepted with probability min(1, e^{-dH}).  The operator may be either
+form of the fermion matrix (HubbardOperator or LinearHubbardOperator); the force is the
+one of that form.
 """
 from __future__ import annotations
 
@@ -13,12 +15,13 @@ import math
 
 import numpy as np
 
-from .hubbard import HubbardOperator, cg_solve, dense_solve, action, force
+from .hubbard import (HubbardOperator, LinearHubbardOperator, cg_solve, dense_solve, dense_solve_op, action,
+                      force, force_linear)
 
 
 def _solve(op, phi, chi, tol, dense):
     if dense:
-        return dense_solve(op, phi, chi)
+        return dense_solve_op(op, phi, chi) if isinstance(op, LinearHubbardOperator) else dense_solve(op, phi, chi)
     x, _, _ = cg_solve(op, phi, chi, tol=tol)
     return x
 
@@ -29,7 +32,8 @@ def hamiltonian(op: HubbardOperator, U: float, phi, pi, chi, x) -> float:
 
 def total_force(op: HubbardOperator, U: float, phi, x) -> np.ndarray:
     """dH/dphi = phi/(delta U) + dS_f/dphi."""
-    return phi / (op.delta * U) + force(op, phi, x)
+    g = force_linear(op, phi, x) if isinstance(op, LinearHubbardOperator) else force(op, phi, x)
+    return phi / (op.delta * U) + g
 
 
 def trajectory(op: HubbardOperator, U: float, phi0, pi0, rho, u: float, n_md: int, eps: float,

@@ -21,6 +21,7 @@ __all__ = ["Hubbard", "CgResult", "HubError", "PseudofermionAction"]
 _PREC = {"fp64": _lib.HUB_PREC_FP64, "mixed": _lib.HUB_PREC_MIXED}
 _PATH = {"auto": _lib.HUB_PATH_AUTO, "fused": _lib.HUB_PATH_FUSED, "split": _lib.HUB_PATH_SPLIT}
 _PATH_NAME = {v: k for k, v in _PATH.items()}
+_FORM = {"exp": _lib.HUB_FORM_EXP, "linear": _lib.HUB_FORM_LINEAR}
 
 
 def _stream_ptr(device) -> ctypes.c_void_p:
@@ -42,17 +43,22 @@ class CgResult:
 
 
 class Hubbard:
-    """One lattice: L x L honeycomb torus (V = 2 L^2 sites), Nt slices, beta, kappa."""
+    """One lattice: L x L honeycomb torus (V = 2 L^2 sites), Nt slices, beta, kappa.
+
+    form="exp" applies the exponential transfer-matrix form of the fermion matrix,
+    form="linear" the linear form of eq. "ferm_op" as printed (mu = 0 only).
+    """
 
     def __init__(self, L: int, Nt: int, beta: float, kappa: float = 1.0, nrhs_max: int = 1,
-                 path: str = "auto", device=None, mu: float = 0.0):
+                 path: str = "auto", device=None, mu: float = 0.0, form: str = "exp"):
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.L, self.Nt, self.beta, self.kappa, self.nrhs_max = L, Nt, float(beta), float(kappa), nrhs_max
         self.mu = float(mu)
+        self.form = form
         self.V = 2 * L * L
         self.N = self.V * Nt
-        prm = _lib.HubParams(L, Nt, float(beta), float(kappa), nrhs_max, _PATH[path], float(mu))
+        prm = _lib.HubParams(L, Nt, float(beta), float(kappa), nrhs_max, _PATH[path], float(mu), _FORM[form])
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self.lib.hub_create(ctypes.byref(prm), _stream_ptr(self.device), ctypes.byref(h)))

@@ -12,12 +12,13 @@ STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_DEVICE", 3: "HUB_ERR_
                 4: "HUB_ERR_NOCONV", 5: "HUB_ERR_NONFINITE"}
 HUB_PREC_FP64, HUB_PREC_MIXED = 0, 1
 HUB_PATH_AUTO, HUB_PATH_FUSED, HUB_PATH_SPLIT = 0, 1, 2
+HUB_FORM_EXP, HUB_FORM_LINEAR = 0, 1
 
 
 class HubParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("Nt", ctypes.c_int32), ("beta", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("nrhs_max", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("mu", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("form", ctypes.c_int32)]
 
 
 class HubCgOpts(ctypes.Structure):

@@ -88,9 +88,19 @@ void allow_lds(K kern, size_t bytes) {
 
 // Which operator kernel runs for nrhs right-hand sides, and how many reduction slots
 // (blocks per right-hand side) it has.
-enum class OpKind { Generic, Whole51, Half51, Split };
+enum class OpKind { Generic, Whole51, Half51, Split, Linear };
+
+// Linear form: chunks per slice so that a launch has at least one workgroup per compute
+// unit (256) where the slice allows it.
+int lin_nch(const hub_ctx* c, int nrhs) {
+    const int slices = nrhs * c->Nt;
+    const int want = (256 + slices - 1) / slices;
+    const int most = (c->V + kLinThreads - 1) / kLinThreads;
+    return std::max(1, std::min(want, most));
+}
 
 OpKind op_kind(const hub_ctx* c, int nrhs) {
+    if (c->form == HUB_FORM_LINEAR) return OpKind::Linear;
     if (c->path == HUB_PATH_SPLIT) return OpKind::Split;
     if (c->L == 51 && c->specialized) return nrhs * c->Nt < kHalfBelow ? OpKind::Half51 : OpKind::Whole51;
     return OpKind::Generic;
@@ -100,6 +110,7 @@ int op_slots(const hub_ctx* c, int nrhs) {
     switch (op_kind(c, nrhs)) {
         case OpKind::Half51: return 2 * c->Nt;
         case OpKind::Split: return 2 * c->Nt * split_geom(c->L).nrb;
+        case OpKind::Linear: return c->Nt * lin_nch(c, nrhs);
         default: return c->Nt;
     }
 }
@@ -131,6 +142,7 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
             return launch_check("k_fused");
         }
         case OpKind::Split:
+        case OpKind::Linear:
             break;
     }
     const SplitGeom G = split_geom(c->L);
@@ -153,6 +165,25 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
     hipLaunchKernelGGL(k3, dim3(nrow_blocks), dim3(kThreads), lds_rows, st, T, G, static_cast<const cx<R>*>(W),
                        epi, ctl);
     return launch_check("k_split_rows_inv");
+}
+
+// Linear form: one stencil launch between a source and an output functor.
+template <typename R>
+LinTab<R> lin_tab(const hub_ctx* c, int nrhs) {
+    const int nch = lin_nch(c, nrhs);
+    return {c->L, c->L * c->L, c->V, c->Nt, nch, (c->V + nch - 1) / nch, c->N, (R)(c->delta * c->kappa)};
+}
+
+constexpr int kLinBatch = 2;   // sites per thread with loads in flight together
+
+template <typename R, bool DAG, class Ph, class Src, class Out, class Ctl>
+hub_status run_lin(hub_ctx* c, int nrhs, const Ph& ph, const Src& src, const Out& out, const Ctl& ctl_in,
+                   hipStream_t st) {
+    const LinTab<R> T = lin_tab<R>(c, nrhs);
+    const Ctl ctl = ctl_in.with_slots(op_slots(c, nrhs));
+    hipLaunchKernelGGL((k_lin<R, DAG, kLinBatch, Ph, Src, Out, Ctl>), dim3(nrhs * c->Nt * T.nch),
+                       dim3(kLinThreads), 0, st, T, ph, src, out, ctl);
+    return launch_check(DAG ? "k_lin<dag>" : "k_lin");
 }
 
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
@@ -180,6 +211,9 @@ hub_status apply_M_impl(hub_ctx* c, const R* phi, const void* in, void* out, int
     hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
+    if (c->form == HUB_FORM_LINEAR)
+        return run_lin<R, false>(c, nrhs, PhAngle<R>{phi}, LSrcVec<R>{v}, LOutStore<R>{static_cast<cx<R>*>(out)},
+                                 CtlPlain{}, static_cast<hipStream_t>(stream));
     return run_op<R>(c, nrhs, SrcPhasePrev<R>{v, PhAngle<R>{phi}}, EpiM<R>{v, static_cast<cx<R>*>(out)},
                      CtlPlain{}, static_cast<hipStream_t>(stream));
 }
@@ -189,6 +223,9 @@ hub_status apply_Mdag_impl(hub_ctx* c, const R* phi, const void* in, void* out, 
     hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
+    if (c->form == HUB_FORM_LINEAR)
+        return run_lin<R, true>(c, nrhs, PhAngle<R>{phi}, LSrcVec<R>{v}, LOutStore<R>{static_cast<cx<R>*>(out)},
+                                CtlPlain{}, static_cast<hipStream_t>(stream));
     return run_op<R>(c, nrhs, SrcNext<R>{v}, EpiMdag<R>{v, static_cast<cx<R>*>(out), PhAngle<R>{phi}},
                      CtlPlain{}, static_cast<hipStream_t>(stream));
 }
@@ -242,6 +279,7 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     CgScalars* sc = c->scal;
     const int zero_start = o.use_x0 ? 0 : 1;
     const int blocks = nrhs * c->Nt;
+    const bool lin = c->form == HUB_FORM_LINEAR;
 
     // ||r||^2 partials of iterations i, i-1, i+1 rotate through three buffers (index i mod 3)
     const int slots = op_slots(c, nrhs);
@@ -259,13 +297,20 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
                            static_cast<const CgScalars*>(sc));
         hub_status r = launch_check("k_fold_solution");
         if (r != HUB_OK) return r;
+        const RedArgs red{c->partials, c->counters + 3, 0, nrhs};
+        const CtlAtomic<FinResidual> fin_ctl{sc, GATE_NOTDONE, red, FinResidual{sc, pr(i), pr(i + 2), slots}};
+        if (lin) {
+            r = run_lin<double, true>(c, nrhs, tab64, LSrcVec<double>{xhi}, LOutStore<double>{tmp},
+                                      CtlGate{sc, GATE_NOTDONE}, st);
+            if (r != HUB_OK) return r;
+            return run_lin<double, false>(c, nrhs, tab64, LSrcVec<double>{tmp}, LOutResidual<Rlo>{chi, rhi, rlo},
+                                          fin_ctl, st);
+        }
         r = run_op<double>(c, nrhs, SrcNext<double>{xhi}, EpiMdag<double, PhTable<double>>{xhi, tmp, tab64},
                            CtlGate{sc, GATE_NOTDONE}, st);
         if (r != HUB_OK) return r;
-        const RedArgs red{c->partials, c->counters + 3, 0, nrhs};
         return run_op<double>(c, nrhs, SrcPhasePrev<double, PhTable<double>>{tmp, tab64},
-                              EpiResidual<Rlo>{tmp, chi, rhi, rlo},
-                              CtlAtomic<FinResidual>{sc, GATE_NOTDONE, red, FinResidual{sc, pr(i), pr(i + 2), slots}}, st);
+                              EpiResidual<Rlo>{tmp, chi, rhi, rlo}, fin_ctl, st);
     };
 
     if (!zero_start) {
@@ -300,11 +345,20 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
         const long long n = std::min<long long>(every, o.max_iter - it);
         for (long long k = 0; k < n; ++k) {
             const long long i = it + k;
+            const CtlSearch k1{pr(i), pr(i + 2), pt, sc, slots};
+            const CtlUpdate k2{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
+            if (lin) {
+                s = run_lin<Rlo, true>(c, nrhs, tab_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
+                if (s != HUB_OK) return s;
+                s = run_lin<Rlo, false>(c, nrhs, tab_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
+                if (s != HUB_OK) return s;
+                continue;
+            }
             s = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p}, EpiSearchMdag<Rlo, PhTable<Rlo>>{rlo, p, tv, tab_lo},
-                            CtlSearch{pr(i), pr(i + 2), pt, sc, slots}, st);
+                            k1, st);
             if (s != HUB_OK) return s;
             s = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhTable<Rlo>>{tv, tab_lo}, EpiUpdate<Rlo>{tv, p, xlo, rlo},
-                            CtlUpdate{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots}, st);
+                            k2, st);
             if (s != HUB_OK) return s;
         }
         it += n;
@@ -340,8 +394,11 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     if (!std::isfinite(prm->beta) || !std::isfinite(prm->kappa) || !std::isfinite(prm->mu))
         return fail(HUB_ERR_ARG, "beta, kappa and mu must be finite");
     if (prm->path < HUB_PATH_AUTO || prm->path > HUB_PATH_SPLIT) return fail(HUB_ERR_ARG, "bad path %d", prm->path);
+    if (prm->form != HUB_FORM_EXP && prm->form != HUB_FORM_LINEAR) return fail(HUB_ERR_ARG, "bad form %d", prm->form);
+    const bool lin = prm->form == HUB_FORM_LINEAR;
+    if (lin && prm->mu != 0.0) return fail(HUB_ERR_ARG, "the linear form is defined at mu = 0 only");
     FftPlan plan{};
-    if (!make_plan(prm->L, &plan))
+    if (!lin && !make_plan(prm->L, &plan))
         return fail(HUB_ERR_ARG, "L=%d has a prime factor above 17", prm->L);
     const long long N = 2LL * prm->L * prm->L * prm->Nt;
     if ((long long)prm->nrhs_max * N >= (1LL << 40)) return fail(HUB_ERR_ARG, "problem too large");
@@ -356,6 +413,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     c->kappa = prm->kappa;
     c->delta = prm->beta / prm->Nt;
     c->plan = plan;
+    c->form = prm->form;
     auto bail = [&](hub_status s) {
         hub_destroy(c);
         return s;
@@ -366,14 +424,14 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     c->lds_fused64 = (int)fused_lds<double>(c);
     c->lds_fused32 = (int)fused_lds<float>(c);
     const int reserve = 1024;   // static LDS of the reduction
-    const bool fits = c->lds_fused64 + reserve <= c->max_lds;
+    const bool fits = lin || c->lds_fused64 + reserve <= c->max_lds;
     if (prm->path == HUB_PATH_FUSED && !fits)
         return bail(fail(HUB_ERR_ARG, "fused path needs %d B of LDS, device has %d", c->lds_fused64, c->max_lds));
     c->path = (prm->path == HUB_PATH_SPLIT || (prm->path == HUB_PATH_AUTO && !fits)) ? HUB_PATH_SPLIT
                                                                                       : HUB_PATH_FUSED;
 
     std::vector<double> roots, etab;
-    build_tables(plan, c->delta * c->kappa, c->delta * prm->mu, roots, etab);
+    if (!lin) build_tables(plan, c->delta * c->kappa, c->delta * prm->mu, roots, etab);
     std::vector<float> roots32(roots.begin(), roots.end()), etab32(etab.begin(), etab.end());
     hipStream_t st = static_cast<hipStream_t>(stream);
 #define CREATE_OR_BAIL(expr)                                                                   \
@@ -383,22 +441,25 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
             return bail(fail(e_ == hipErrorOutOfMemory ? HUB_ERR_NOMEM : HUB_ERR_DEVICE,       \
                              "%s failed: %s", #expr, hipGetErrorString(e_)));                  \
     } while (0)
-    CREATE_OR_BAIL(hipMalloc(&c->roots64, roots.size() * sizeof(double)));
-    CREATE_OR_BAIL(hipMalloc(&c->roots32, roots.size() * sizeof(float)));
-    CREATE_OR_BAIL(hipMalloc(&c->etab64, etab.size() * sizeof(double)));
-    CREATE_OR_BAIL(hipMalloc(&c->etab32, etab.size() * sizeof(float)));
-    CREATE_OR_BAIL(hipMemcpyAsync(c->roots64, roots.data(), roots.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    CREATE_OR_BAIL(hipMemcpyAsync(c->roots32, roots32.data(), roots32.size() * sizeof(float), hipMemcpyHostToDevice, st));
-    CREATE_OR_BAIL(hipMemcpyAsync(c->etab64, etab.data(), etab.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    CREATE_OR_BAIL(hipMemcpyAsync(c->etab32, etab32.data(), etab32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    if (!lin) {
+        CREATE_OR_BAIL(hipMalloc(&c->roots64, roots.size() * sizeof(double)));
+        CREATE_OR_BAIL(hipMalloc(&c->roots32, roots.size() * sizeof(float)));
+        CREATE_OR_BAIL(hipMalloc(&c->etab64, etab.size() * sizeof(double)));
+        CREATE_OR_BAIL(hipMalloc(&c->etab32, etab.size() * sizeof(float)));
+        CREATE_OR_BAIL(hipMemcpyAsync(c->roots64, roots.data(), roots.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        CREATE_OR_BAIL(hipMemcpyAsync(c->roots32, roots32.data(), roots32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+        CREATE_OR_BAIL(hipMemcpyAsync(c->etab64, etab.data(), etab.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        CREATE_OR_BAIL(hipMemcpyAsync(c->etab32, etab32.data(), etab32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    }
 
     const SplitGeom G = split_geom(c->L);
     c->max_partials = std::max(2 * c->Nt, c->Nt * 2 * G.nrb);
+    c->max_partials = std::max(c->max_partials, c->Nt * lin_nch(c, 1));
     CREATE_OR_BAIL(hipMalloc(&c->partials, (size_t)c->nrhs_max * c->max_partials * sizeof(double)));
     CREATE_OR_BAIL(hipMalloc(&c->counters, kNumCounters * sizeof(unsigned int)));
     CREATE_OR_BAIL(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(unsigned int), st));
     CREATE_OR_BAIL(hipMalloc(&c->red_out, 8 * sizeof(double)));
-    if (c->path == HUB_PATH_SPLIT)
+    if (c->path == HUB_PATH_SPLIT && !lin)
         CREATE_OR_BAIL(hipMalloc(&c->split_w, (size_t)c->nrhs_max * c->N * sizeof(cx<double>)));
     CREATE_OR_BAIL(hipStreamSynchronize(st));   // host vectors above go out of scope
 #undef CREATE_OR_BAIL
@@ -457,6 +518,11 @@ hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, in
         return fail(HUB_ERR_ARG, "dSdphi overlaps phi");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const cx<double>* xv = static_cast<const cx<double>*>(x);
+    if (c->form == HUB_FORM_LINEAR) {
+        const int blocks = (int)std::min<long long>((c->N + kThreads - 1) / kThreads, 4096);
+        hipLaunchKernelGGL(k_lin_force, dim3(blocks), dim3(kThreads), 0, st, lin_tab<double>(c, 1), phi, xv, g, nrhs);
+        return launch_check("k_lin_force");
+    }
     if (nrhs == 1)
         return run_op<double>(c, 1, SrcNext<double>{xv}, EpiForce{xv, {phi}, g, 0}, CtlPlain{}, st);
     if (!c->force_tmp) HIP_OR_FAIL(hipMalloc(&c->force_tmp, (size_t)c->nrhs_max * c->N * sizeof(double)));
@@ -506,6 +572,11 @@ hub_status hub_boson_energy(hub_ctx* c, const double* phi, const double* pi, dou
 
 hub_status hub_query(const hub_ctx* c, int32_t* path, int32_t* lds_bytes) {
     if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (c->form == HUB_FORM_LINEAR) {
+        if (path) *path = HUB_PATH_FUSED;
+        if (lds_bytes) *lds_bytes = 0;
+        return HUB_OK;
+    }
     if (path) *path = c->path;
     if (lds_bytes) {
         const SplitGeom G = split_geom(c->L);

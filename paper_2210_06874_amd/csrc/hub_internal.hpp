@@ -39,6 +39,7 @@ struct hub_ctx {
     long long N = 0;                 // V * Nt
     double beta = 0, kappa = 0, delta = 0;
     int path = HUB_PATH_FUSED;
+    int form = HUB_FORM_EXP;
     bool specialized = true;         // use a compile-time-L kernel when one exists
     int lds_fused64 = 0, lds_fused32 = 0;
     int max_lds = 0;

@@ -838,6 +838,246 @@ k_split_rows_inv(const OpTab<R> T, const SplitGeom G, const cx<R>* __restrict__ 
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
 }
 
+// ----------------------------------------------------------------------------- linear form
+// The fermion matrix as printed in Sec. 2, eq. "ferm_op" (linear in delta*kappa) is a
+// nearest-neighbour stencil in space and time: for destination (t, x)
+//     M,     A site:  B_{t+1} v_{t+1,x} - e^{i phi_{t,x}}  v_{t,x} - dk sum_y v_{t,y}
+//     M,     B site:  v_{t,x} - B_t e^{-i phi_{t,x}} v_{t-1,x}      - dk sum_y v_{t,y}
+//     M^dag, A site:  B_t v_{t-1,x} - e^{-i phi_{t,x}} v_{t,x}      - dk sum_y v_{t,y}
+//     M^dag, B site:  v_{t,x} - B_{t+1} e^{i phi_{t+1,x}} v_{t+1,x} - dk sum_y v_{t,y}
+// (y over the three neighbours on the other sublattice, B_0 = -1).  Every output is one
+// diagonal term, one time hop and three equal-time hops, so the kernel streams its
+// vectors once from HBM; the neighbour entries are re-read from the caches.
+constexpr int kLinThreads = 1024;
+
+template <typename R>
+struct LinTab {
+    int L, LL, V, Nt;
+    int nch, chunk;              // chunks per slice, sites per chunk
+    long long N;
+    R dk;
+};
+
+// A linear-form source supplies the vector the operator acts on, entry by entry.
+template <typename R>
+struct LSrcVec {                 // v
+    using Pre = cx<R>;
+    const cx<R>* v;
+    __device__ Pre fetch(long long k) const { return v[k]; }
+    __device__ cx<R> make(const Pre& a, const Scal&) const { return a; }
+};
+
+template <typename R>
+struct LSrcSearch {              // r + beta p                          (CG: the new direction)
+    using Pre = PrePair<R>;
+    const cx<R>* r;
+    const cx<R>* p;
+    __device__ Pre fetch(long long k) const { return {r[k], p[k]}; }
+    __device__ cx<R> make(const Pre& a, const Scal& s) const {
+        const R b = (R)s.beta;
+        return {a.a.re + b * a.b.re, a.a.im + b * a.b.im};
+    }
+};
+
+// A linear-form output receives the operator's value o at entry k.
+template <typename R>
+struct LOutStore {               // out = o
+    using Pre = int;
+    cx<R>* out;
+    __device__ Pre fetch(long long) const { return 0; }
+    __device__ void store(long long k, cx<R> o, const Pre&, const Scal&, double&) const { out[k] = o; }
+};
+
+template <typename R>
+struct LOutSearch {              // CG: tv = M^dag (r + beta p); acc |tv|^2
+    using Pre = int;
+    cx<R>* tv;
+    __device__ Pre fetch(long long) const { return 0; }
+    __device__ void store(long long k, cx<R> o, const Pre&, const Scal&, double& acc) const {
+        tv[k] = o;
+        acc += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+    }
+};
+
+template <typename R>
+struct LPreUpdate {
+    cx<R> p, x, r;
+};
+
+template <typename R>
+struct LOutUpdate {              // CG: q = M tv; p = r + beta p; x += alpha p; r -= alpha q; acc |r|^2
+    using Pre = LPreUpdate<R>;
+    cx<R>* p;
+    cx<R>* x;
+    cx<R>* r;
+    __device__ Pre fetch(long long k) const { return {p[k], x[k], r[k]}; }
+    __device__ void store(long long k, cx<R> q, const Pre& a, const Scal& sc, double& acc) const {
+        const R b = (R)sc.beta, al = (R)sc.alpha;
+        const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
+        const cx<R> rn = {a.r.re - al * q.re, a.r.im - al * q.im};
+        p[k] = pn;
+        x[k] = {a.x.re + al * pn.re, a.x.im + al * pn.im};
+        r[k] = rn;
+        acc += (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
+    }
+};
+
+template <typename Rlo>
+struct LOutResidual {            // FP64: r_hi = chi - o (o = M M^dag x_hi); r_lo = r_hi; acc |r_hi|^2
+    using Pre = cx<double>;
+    const cx<double>* chi;
+    cx<double>* rhi;
+    cx<Rlo>* rlo;
+    __device__ Pre fetch(long long k) const { return chi[k]; }
+    __device__ void store(long long k, cx<double> o, const Pre& c, const Scal&, double& acc) const {
+        const cx<double> rv = c - o;
+        rhi[k] = rv;
+        rlo[k] = {(Rlo)rv.re, (Rlo)rv.im};
+        acc += rv.re * rv.re + rv.im * rv.im;
+    }
+};
+
+// Where the stencil of site i reads: the three neighbours on the other sublattice
+// (A(n) - B(n), B(n - e1), B(n - e2); cell n = (n1, n2), x = s L^2 + n1 L + n2).
+__device__ __forceinline__ void lin_neighbours(int i, int L, int LL, int nb[3]) {
+    const int s = i >= LL ? 1 : 0;
+    const int n = i - s * LL;
+    const int n1 = n / L, n2 = n - n1 * L;
+    if (s == 0) {
+        nb[0] = LL + n;
+        nb[1] = LL + (n1 == 0 ? L - 1 : n1 - 1) * L + n2;
+        nb[2] = LL + n1 * L + (n2 == 0 ? L - 1 : n2 - 1);
+    } else {
+        nb[0] = n;
+        nb[1] = (n1 == L - 1 ? 0 : n1 + 1) * L + n2;
+        nb[2] = n1 * L + (n2 == L - 1 ? 0 : n2 + 1);
+    }
+}
+
+template <typename R, class Src, class Ph>
+struct LinPre {
+    typename Src::Pre own, hop, nb[3];
+    typename Ph::Pre ph;
+};
+
+// One workgroup per (right-hand side, slice, chunk of sites); NB sites per thread have all
+// their loads in flight before the first is used.
+template <typename R, bool DAG, int NB, class Ph, class Src, class Out, class Ctl>
+__global__ void __launch_bounds__(kLinThreads)
+k_lin(const LinTab<R> T, const Ph ph, const Src src, const Out out, const Ctl ctl) {
+    __shared__ double red_lds[64];
+    const int u = xcd_linear(blockIdx.x, gridDim.x);
+    const int per_rhs = T.Nt * T.nch;
+    const int rhs = u / per_rhs, slot = u - rhs * per_rhs;
+    const int t = slot / T.nch, ch = slot - t * T.nch;
+    const Scal sc = ctl.begin(rhs, slot, red_lds);
+    double acc = 0.0;
+    if (sc.open) {
+        const int i0 = ch * T.chunk;
+        const int i1 = min(T.V, i0 + T.chunk);
+        const int tp = prev_slice(t, T.Nt), tn = next_slice(t, T.Nt);
+        const long long vb = rhs * T.N;
+        const long long row = (long long)t * T.V;
+        // A sites hop to t+1 (M) or t-1 (M^dag); B sites the other way
+        const long long rowA = (long long)(DAG ? tp : tn) * T.V;
+        const long long rowB = (long long)(DAG ? tn : tp) * T.V;
+        const R sgnA = (DAG ? t == 0 : t == T.Nt - 1) ? (R)-1 : (R)1;
+        const R sgnB = (DAG ? t == T.Nt - 1 : t == 0) ? (R)-1 : (R)1;
+        const long long phB = DAG ? (long long)tn * T.V : row;   // phase slice of the B-site hop
+        for (int base = i0 + (int)threadIdx.x; base < i1; base += NB * kLinThreads) {
+            LinPre<R, Src, Ph> pre[NB];
+            typename Out::Pre op[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int i = base + j * kLinThreads;
+                if (i < i1) {
+                    int nb[3];
+                    lin_neighbours(i, T.L, T.LL, nb);
+                    const bool a = i < T.LL;
+                    pre[j].own = src.fetch(vb + row + i);
+                    pre[j].hop = src.fetch(vb + (a ? rowA : rowB) + i);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) pre[j].nb[m] = src.fetch(vb + row + nb[m]);
+                    pre[j].ph = ph.fetch((a ? row : phB) + i);
+                    op[j] = out.fetch(vb + row + i);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int i = base + j * kLinThreads;
+                if (i < i1) {
+                    const bool a = i < T.LL;
+                    const cx<R> v = src.make(pre[j].own, sc);
+                    const cx<R> h = src.make(pre[j].hop, sc);
+                    cx<R> s3 = src.make(pre[j].nb[0], sc);
+                    s3 = s3 + src.make(pre[j].nb[1], sc);
+                    s3 = s3 + src.make(pre[j].nb[2], sc);
+                    const cx<R> e = ph.value(pre[j].ph);
+                    // e^{+i phi} for M on A sites and M^dag on B sites, e^{-i phi} otherwise
+                    const cx<R> f = (a != DAG) ? e : cx<R>{e.re, -e.im};
+                    cx<R> o;
+                    if (a) {                                  // sgn h - f v
+                        const cx<R> fv = cmul(f, v);
+                        o = {sgnA * h.re - fv.re, sgnA * h.im - fv.im};
+                    } else {                                  // v - sgn f h
+                        const cx<R> fh = cmul(f, h);
+                        o = {v.re - sgnB * fh.re, v.im - sgnB * fh.im};
+                    }
+                    o = {o.re - T.dk * s3.re, o.im - T.dk * s3.im};
+                    out.store(vb + row + i, o, op[j], sc, acc);
+                }
+            }
+        }
+    }
+    if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
+}
+
+// Force of the linear form, summed over right-hand sides, with y = M^dag x formed where
+// it is needed (phi_{t,z} enters one entry of M):
+//     A site:  g = -2 Im(e^{i phi_{t,z}} conj(x_{t,z}) y_{t,z})
+//     B site:  g = 2 B_t Im(e^{-i phi_{t,z}} conj(x_{t,z}) y_{t-1,z})
+// One thread per (t, z).
+__global__ void __launch_bounds__(kThreads)
+k_lin_force(const LinTab<double> T, const double* __restrict__ phi, const cx<double>* __restrict__ x,
+            double* __restrict__ g, int nrhs) {
+    const long long n = T.N;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x) {
+        const int t = (int)(k / T.V), i = (int)(k - (long long)t * T.V);
+        const bool a = i < T.LL;
+        const int tp = prev_slice(t, T.Nt);
+        int nb[3];
+        lin_neighbours(i, T.L, T.LL, nb);
+        double s, c;
+        phase_sincos(phi[k], &s, &c);
+        const double bt = t == 0 ? -1.0 : 1.0;
+        // y at (ty, i): A sites y_{t} = B_t x_{t-1} - e^{-i phi_t} x_t - dk sum x_{t,nb};
+        //               B sites y_{t-1} = x_{t-1} - B_t e^{i phi_t} x_t - dk sum x_{t-1,nb}
+        const long long ry = (long long)(a ? t : tp) * T.V;
+        double acc = 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+            const cx<double>* xv = x + r * n;
+            const cx<double> xt = xv[k], xp = xv[(long long)tp * T.V + i];
+            cx<double> s3 = xv[ry + nb[0]];
+            s3 = s3 + xv[ry + nb[1]];
+            s3 = s3 + xv[ry + nb[2]];
+            cx<double> y;
+            if (a) {
+                const cx<double> ex = cmulc(xt, cx<double>{c, s});     // e^{-i phi} x_t
+                y = {bt * xp.re - ex.re - T.dk * s3.re, bt * xp.im - ex.im - T.dk * s3.im};
+                const cx<double> z = cmul(cx<double>{c, s}, cmulc(y, xt));   // e^{i phi} conj(x) y
+                acc += -2.0 * z.im;
+            } else {
+                const cx<double> ex = cmul(xt, cx<double>{c, s});      // e^{i phi} x_t
+                y = {xp.re - bt * ex.re - T.dk * s3.re, xp.im - bt * ex.im - T.dk * s3.im};
+                const cx<double> z = cmulc(cmulc(y, xt), cx<double>{c, s});  // e^{-i phi} conj(x) y
+                acc += 2.0 * bt * z.im;
+            }
+        }
+        g[k] = acc;
+    }
+}
+
 // ----------------------------------------------------------------------------- elementwise kernels
 // One block per (right-hand side, slice); reductions in slice order.
 template <typename Rlo>

@@ -5,9 +5,10 @@
 #include "hub.h"
 
 int main(void) {
-    printf("hub_params %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hub_params), offsetof(hub_params, L),
+    printf("hub_params %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hub_params), offsetof(hub_params, L),
            offsetof(hub_params, Nt), offsetof(hub_params, beta), offsetof(hub_params, kappa),
-           offsetof(hub_params, nrhs_max), offsetof(hub_params, path), offsetof(hub_params, mu));
+           offsetof(hub_params, nrhs_max), offsetof(hub_params, path), offsetof(hub_params, mu),
+           offsetof(hub_params, form));
     printf("hub_cg_opts %zu %zu %zu %zu %zu %zu\n", sizeof(hub_cg_opts), offsetof(hub_cg_opts, tol),
            offsetof(hub_cg_opts, max_iter), offsetof(hub_cg_opts, reliable_every), offsetof(hub_cg_opts, prec),
            offsetof(hub_cg_opts, use_x0));

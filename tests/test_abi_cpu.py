@@ -54,10 +54,12 @@ def test_argument_errors_before_any_device_call():
     assert lib.hub_create(None, None, ctypes.byref(h)) == L.HUB_ERR_ARG
     assert b"NULL" in lib.hub_last_error()
     for bad in [dict(L=0), dict(L=19), dict(L=2048), dict(Nt=0), dict(nrhs_max=0), dict(path=7),
-                dict(beta=float("nan")), dict(mu=float("inf"))]:
-        prm = dict(L=3, Nt=8, beta=2.0, kappa=1.0, nrhs_max=1, path=0, mu=0.0)
+                dict(beta=float("nan")), dict(mu=float("inf")), dict(form=2), dict(form=-1),
+                dict(form=1, mu=0.5), dict(form=1, L=1025)]:
+        prm = dict(L=3, Nt=8, beta=2.0, kappa=1.0, nrhs_max=1, path=0, mu=0.0, form=0)
         prm.update(bad)
-        p = L.HubParams(prm["L"], prm["Nt"], prm["beta"], prm["kappa"], prm["nrhs_max"], prm["path"], prm["mu"])
+        p = L.HubParams(prm["L"], prm["Nt"], prm["beta"], prm["kappa"], prm["nrhs_max"], prm["path"], prm["mu"],
+                        prm["form"])
         assert lib.hub_create(ctypes.byref(p), None, ctypes.byref(h)) == L.HUB_ERR_ARG, bad
         assert h.value is None
     assert lib.hub_create(ctypes.byref(L.HubParams(3, 8, 2.0, 1.0, 1, 0, 0.0)), None, None) == L.HUB_ERR_ARG
