@@ -16,6 +16,8 @@ Also measured (not part of `value`):
   * the FP64 force step (s per force, FP64 vs mixed);
   * back-to-back hub_apply_M_c64 / hub_apply_M launches timed with HIP events on
     the launching stream: the roofline of the dominant kernel;
+  * the same force step with the linear form of the operator (eq. "ferm_op" as printed,
+    a nearest-neighbour stencil) and the roofline of its FP32 apply;
   * the CPU oracle (rank 0, N = 1 only) on a bounded sample of operator applications.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -34,6 +36,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "M-applications/s & s per HMC force, L=51 Nt=128, FP32-mixed vs FP64 @1e-10 res"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_M_c64_L51_Nt128.txt")
+TRAFFIC_FILE_LIN = os.path.join(ROOT, "profiles", "traffic_apply_M_c64_linear_L51_Nt128.txt")
 KERNEL_SOURCES = ["hub_fft.hpp", "hub_kernels.hpp", "hub_math.hpp", "hub_abi.hip", "hub_tables.cpp",
                   "hub_tables.hpp", "hub_internal.hpp"]
 
@@ -47,13 +50,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(n_entries: int):
-    """HBM bytes per launch of the FP32 operator kernel from the committed rocprofv3
+def read_traffic(path: str = TRAFFIC_FILE):
+    """HBM bytes per launch of an FP32 operator kernel from the committed rocprofv3
     counter summary, or None when absent or taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -128,6 +131,41 @@ def cpu_baseline(w, phi, chi, budget_s: float = 15.0):
                       f"{blas[0]['internal_api'] if blas else 'none'} unused"}
 
 
+def linear_leg(w, dev, P, C, P32, V32, out32, steps: int, warmup: int) -> dict:
+    """The force step and the FP32 apply roofline with the linear form of the operator."""
+    import torch
+    from paper_2210_06874_amd import Hubbard
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, device=dev, form="linear")
+    out = {}
+    for prec in ("mixed", "fp64"):
+        for _ in range(max(1, warmup)):
+            hub.cg_solve(P, C, tol=1e-10, prec=prec, max_iter=200000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        applies = 0
+        for _ in range(steps):
+            res = hub.cg_solve(P, C, tol=1e-10, prec=prec, max_iter=200000)
+            hub.force(P, res.x)
+            hub.action(C, res.x)
+            applies += 2 * res.iters[0] + 2 * res.reliable_updates[0] + 1
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = {"s_per_force": dt / steps, "applications_per_s": applies / dt, "cg_iters": res.iters[0],
+                     "reliable_updates": res.reliable_updates[0], "true_rel_res": res.true_rel_res[0]}
+    t_k = time_graph(lambda: hub.apply_M_c64(P32, V32, out=out32))
+    out64 = torch.empty_like(C)
+    t_k64 = time_graph(lambda: hub.apply_M(P, C, out=out64))
+    alg = 20.0 * w.N
+    out["roofline"] = {"bound": "hbm", "achieved": alg / t_k / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": alg / t_k / 1e9 / HBM_PEAK_GBS, "traffic": read_traffic(TRAFFIC_FILE_LIN),
+                       "kernel": "hub_apply_M_c64, linear form (k_lin<float, ...>)",
+                       "avg_launch_us": t_k * 1e6, "alg_bytes_per_launch": alg,
+                       "timing": "HIP graph of 50 launches, events on its stream"}
+    out["roofline_apply_M_fp64"] = {"achieved": 2 * alg / t_k64 / 1e9, "frac": 2 * alg / t_k64 / 1e9 / HBM_PEAK_GBS,
+                                    "avg_launch_us": t_k64 * 1e6, "alg_bytes_per_launch": 2 * alg}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,8 +197,11 @@ def main() -> int:
         P32 = torch.from_numpy(phi).to(dev).float()
         V32 = torch.from_numpy(chi).to(dev).to(torch.complex64)
         out32 = torch.empty_like(V32)
+        hub_lin = Hubbard(w.L, w.Nt, w.beta, w.kappa, device=dev, form="linear")
         for _ in range(20):
             hub.apply_M_c64(P32, V32, out=out32)
+        for _ in range(20):
+            hub_lin.apply_M_c64(P32, V32, out=out32)
         a = torch.full((16 * 1024 * 1024,), 1.0, dtype=torch.float32, device=dev)   # 64 MiB
         b = torch.empty_like(a)
         for _ in range(5):
@@ -216,7 +257,7 @@ def main() -> int:
     t_loop32 = time_launches(lambda: hub.apply_M_c64(P32, V32, out=out32), 300)
     alg32 = 20.0 * w.N          # read v (8N) + phi (4N), write out (8N)
     alg64 = 40.0 * w.N
-    traffic = read_traffic(w.N)
+    traffic = read_traffic(TRAFFIC_FILE)
     roof = {"bound": "hbm", "achieved": alg32 / t_k32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": alg32 / t_k32 / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "hub_apply_M_c64 (k_fused_ct<float, 51, ...> two workgroups per slice)",
@@ -224,6 +265,8 @@ def main() -> int:
             "alg_bytes_per_launch": alg32, "timing": "HIP graph of 50 launches, events on its stream"}
     roof64 = {"achieved": alg64 / t_k64 / 1e9, "frac": alg64 / t_k64 / 1e9 / HBM_PEAK_GBS,
               "avg_launch_us": t_k64 * 1e6, "alg_bytes_per_launch": alg64}
+
+    lin = linear_leg(w, dev, P, C, P32, V32, out32, args.steps, args.warmup)
 
     probe = None
     if args.literal_probe > 0:
@@ -266,6 +309,7 @@ def main() -> int:
         "force_rel_diff_mixed_vs_fp64": force_diff,
         "roofline": roof,
         "roofline_apply_M_fp64": roof64,
+        "linear_form": lin,
         "literal_field_probe": probe,
         "cpu_baseline": None,
     }

@@ -90,13 +90,25 @@ void allow_lds(K kern, size_t bytes) {
 // (blocks per right-hand side) it has.
 enum class OpKind { Generic, Whole51, Half51, Split, Linear };
 
-// Linear form: chunks per slice so that a launch has at least one workgroup per compute
-// unit (256) where the slice allows it.
+#ifndef HUB_LIN_BATCH
+#define HUB_LIN_BATCH 3
+#endif
+#ifndef HUB_LIN_TARGET
+#define HUB_LIN_TARGET 256
+#endif
+constexpr int kLinBatch = HUB_LIN_BATCH;     // sites per thread with loads in flight together
+constexpr int kLinTarget = HUB_LIN_TARGET;   // fewest workgroups per launch worth splitting slices for
+
+// Linear form: chunks per slice.  Enough workgroups to fill the chip (kLinTarget), and
+// chunks small enough for one batch of loads per thread, while the reduction slots per
+// right-hand side (Nt * chunks, summed by every workgroup of the next CG kernel) stay
+// at most 1024; every chunk holds at least one wavefront of sites.
 int lin_nch(const hub_ctx* c, int nrhs) {
     const int slices = nrhs * c->Nt;
-    const int want = (256 + slices - 1) / slices;
-    const int most = (c->V + kLinThreads - 1) / kLinThreads;
-    return std::max(1, std::min(want, most));
+    int n = std::max((kLinTarget + slices - 1) / slices, (c->V + kLinBatch * kLinThreads - 1) / (kLinBatch * kLinThreads));
+    n = std::min(n, std::max(1, 1024 / c->Nt));
+    n = std::min(n, (c->V + 63) / 64);
+    return std::max(1, n);
 }
 
 OpKind op_kind(const hub_ctx* c, int nrhs) {
@@ -173,8 +185,6 @@ LinTab<R> lin_tab(const hub_ctx* c, int nrhs) {
     const int nch = lin_nch(c, nrhs);
     return {c->L, c->L * c->L, c->V, c->Nt, nch, (c->V + nch - 1) / nch, c->N, (R)(c->delta * c->kappa)};
 }
-
-constexpr int kLinBatch = 2;   // sites per thread with loads in flight together
 
 template <typename R, bool DAG, class Ph, class Src, class Out, class Ctl>
 hub_status run_lin(hub_ctx* c, int nrhs, const Ph& ph, const Src& src, const Out& out, const Ctl& ctl_in,

@@ -66,6 +66,38 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* l
     return block_allsum(v, lds);
 }
 
+// K sums of `n` partials each, in slot order, returned to every thread: all loads are
+// issued before the first is used and the K block reductions share one pair of barriers.
+// Every block of a kernel forms the same sums (the order depends only on blockDim).
+// `lds` needs K * (waves per block) doubles.
+template <int K>
+__device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], int n, double* lds, double (&out)[K]) {
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += p[k][j];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[wave * K + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[w * K + k];
+        out[k] = s;
+    }
+    __syncthreads();
+}
+
 // What an operator kernel's block learns before it starts: whether it works at all,
 // and the CG step scalars.
 struct Scal {
@@ -74,7 +106,8 @@ struct Scal {
 };
 
 // Store this block's partial, and let the block that arrives last sum every right-hand
-// side's partials in slot order and call fin(rhs, sum).  Deterministic: the final sums
+// side's partials in slot order and call fin.finish(rhs, sum, lds) in all of its threads.
+// Deterministic: the final sums
 // never depend on arrival order.  `lds` needs 64 doubles.
 //
 // The partials and the arrival counter are device-scope relaxed atomics (coherent
@@ -102,8 +135,7 @@ __device__ __forceinline__ void reduce_and_finalize(double acc, int rhs, int slo
         for (int j = threadIdx.x; j < ra.slots; j += blockDim.x)
             v += __hip_atomic_load(&ra.partials[(long long)r * ra.slots + j], __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-        const double tot = block_sum(v, lds);
-        if (threadIdx.x == 0) fin(r, tot);
+        fin.finish(r, block_allsum(v, lds), lds);
     }
     if (threadIdx.x == 0) __hip_atomic_store(ra.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -348,39 +380,41 @@ __device__ __forceinline__ cx<R> src_apply(const Src& src, int rhs, int ts, int 
 }
 
 // ----------------------------------------------------------------------------- finalizers
-// Called by thread 0 of the block that arrives last, once per right-hand side in order.
+// finish(r, total, lds) is called by every thread of the block that arrives last, once per
+// right-hand side in order, with the right-hand side's total (the same in every thread).
+// Finalizers without block-wide work act in thread 0 only.
 struct FinResidual {             // after an FP64 residual recomputation (CG reliable update)
     CgScalars* sc;
     double* rr_cur;              // ||r||^2 partials the next CG iteration starts from, [nrhs][slots]
     double* rr_prev;             // and those of the iteration before
     int slots;
-    __device__ void operator()(int r, double rr) const {
-        if (sc[r].done) return;
+    __device__ void finish(int r, double rr, double* lds) const {
+        if (sc[r].done) return;                  // uniform: read before any thread writes
         double* cur = rr_cur + (long long)r * slots;
         double* prev = rr_prev + (long long)r * slots;
-        double rec = 0.0, old = 0.0;
-        for (int j = 0; j < slots; ++j) {
-            rec += cur[j];
-            old += prev[j];
+        const double* const p[2] = {cur, prev};
+        double sum[2];
+        sum_partials_k<2>(p, slots, lds, sum);
+        const double rec = sum[0], old = sum[1];
+        const bool ok = isfinite(rr);
+        if (threadIdx.x == 0) {
+            sc[r].reliable += 1;
+            sc[r].rec_rr = rec;
+            sc[r].true_rr = rr;
+            if (!ok) sc[r].nonfinite = 1;
+            else sc[r].rr = rr;
+            if (ok && rr <= sc[r].tol2) sc[r].done = 1;
         }
-        sc[r].reliable += 1;
-        sc[r].rec_rr = rec;
-        sc[r].true_rr = rr;
-        if (!isfinite(rr)) {
-            sc[r].nonfinite = 1;
-            return;
-        }
-        sc[r].rr = rr;
+        if (!ok) return;
         // The iteration continues from the recomputed residual: alpha uses ||r_true||^2,
         // while the search direction keeps the recursion's beta = rec / old (the previous
-        // entry is rescaled so that the ratio the next kernel forms is unchanged).
-        cur[0] = rr;
-        for (int j = 1; j < slots; ++j) cur[j] = 0.0;
-        if (rec > 0.0 && isfinite(rec)) {
-            prev[0] = old * (rr / rec);
-            for (int j = 1; j < slots; ++j) prev[j] = 0.0;
+        // entry is rescaled so that the ratio the next kernel forms is unchanged).  Every
+        // thread has read the partials (sum_partials_k ends in a barrier) before they change.
+        const bool rescale = rec > 0.0 && isfinite(rec);
+        for (int j = threadIdx.x; j < slots; j += blockDim.x) {
+            cur[j] = j == 0 ? rr : 0.0;
+            if (rescale) prev[j] = j == 0 ? old * (rr / rec) : 0.0;
         }
-        if (rr <= sc[r].tol2) sc[r].done = 1;
     }
 };
 
@@ -390,7 +424,8 @@ struct FinInit {                 // ||chi||^2 and the starting state of every ri
     double* rr0;                 // ||r||^2 partials of iteration 0, [nrhs][slots]
     double* rr_prev;             // and of "iteration -1" (only their ratio with rr0 is used, times p = 0)
     int slots;
-    __device__ void operator()(int r, double cc) const {
+    __device__ void finish(int r, double cc, double*) const {
+        if (threadIdx.x != 0) return;
         CgScalars s{};
         s.chichi = cc;
         s.tol2 = tol * tol * cc;
@@ -412,8 +447,8 @@ struct FinInit {                 // ||chi||^2 and the starting state of every ri
 struct FinStore {                // out[0] = sum over right-hand sides (in order)
     double* out;
     int nrhs;
-    __device__ void operator()(int r, double v) const {
-        out[0] = (r == 0) ? v : out[0] + v;
+    __device__ void finish(int r, double v, double*) const {
+        if (threadIdx.x == 0) out[0] = (r == 0) ? v : out[0] + v;
     }
 };
 
@@ -467,8 +502,11 @@ struct CtlSearch {
     CgScalars* sc;
     int slots;
     __device__ Scal begin(int rhs, int slot, double* lds) const {
-        const double a = sum_partials(rr_i + (long long)rhs * slots, slots, lds);
-        const double b = sum_partials(rr_im1 + (long long)rhs * slots, slots, lds);
+        const long long o = (long long)rhs * slots;
+        const double* const p[2] = {rr_i + o, rr_im1 + o};
+        double sum[2];
+        sum_partials_k<2>(p, slots, lds, sum);
+        const double a = sum[0], b = sum[1];
         const CgScalars& s = sc[rhs];
         int open = (!s.done && !s.nonfinite && a > s.tol2) ? 1 : 0;
         const double beta = a / b;
@@ -497,9 +535,11 @@ struct CtlUpdate {
     CgScalars* sc;
     int slots;
     __device__ Scal begin(int rhs, int slot, double* lds) const {
-        const double a = sum_partials(rr_i + (long long)rhs * slots, slots, lds);
-        const double b = sum_partials(rr_im1 + (long long)rhs * slots, slots, lds);
-        const double c = sum_partials(tt + (long long)rhs * slots, slots, lds);
+        const long long o = (long long)rhs * slots;
+        const double* const p[3] = {rr_i + o, rr_im1 + o, tt + o};
+        double sum[3];
+        sum_partials_k<3>(p, slots, lds, sum);
+        const double a = sum[0], b = sum[1], c = sum[2];
         const CgScalars& s = sc[rhs];
         int open = (!s.done && !s.nonfinite && a > s.tol2) ? 1 : 0;
         const double alpha = a / c, beta = a / b;
@@ -848,7 +888,10 @@ k_split_rows_inv(const OpTab<R> T, const SplitGeom G, const cx<R>* __restrict__ 
 // (y over the three neighbours on the other sublattice, B_0 = -1).  Every output is one
 // diagonal term, one time hop and three equal-time hops, so the kernel streams its
 // vectors once from HBM; the neighbour entries are re-read from the caches.
-constexpr int kLinThreads = 1024;
+#ifndef HUB_LIN_THREADS
+#define HUB_LIN_THREADS 512
+#endif
+constexpr int kLinThreads = HUB_LIN_THREADS;
 
 template <typename R>
 struct LinTab {
@@ -960,8 +1003,47 @@ struct LinPre {
     typename Ph::Pre ph;
 };
 
-// One workgroup per (right-hand side, slice, chunk of sites); NB sites per thread have all
-// their loads in flight before the first is used.
+// One workgroup per (right-hand side, slice, chunk of sites).  The first NB sites of each
+// thread have every load issued before the block learns its CG scalars (the loads do not
+// depend on them), so the scalar reduction and the data fetch overlap; sites beyond
+// NB * kLinThreads per chunk follow in further batches.
+template <typename R, bool DAG, class Ph, class Src>
+__device__ __forceinline__ void lin_fetch(const LinTab<R>& T, const Ph& ph, const Src& src, int i, long long vb,
+                                          long long row, long long rowA, long long rowB, long long phB,
+                                          LinPre<R, Src, Ph>& pre) {
+    int nb[3];
+    lin_neighbours(i, T.L, T.LL, nb);
+    const bool a = i < T.LL;
+    pre.own = src.fetch(vb + row + i);
+    pre.hop = src.fetch(vb + (a ? rowA : rowB) + i);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) pre.nb[m] = src.fetch(vb + row + nb[m]);
+    pre.ph = ph.fetch((a ? row : phB) + i);
+}
+
+template <typename R, bool DAG, class Ph, class Src>
+__device__ __forceinline__ cx<R> lin_value(const LinTab<R>& T, const Ph& ph, const Src& src, int i, R sgnA, R sgnB,
+                                           const LinPre<R, Src, Ph>& pre, const Scal& sc) {
+    const bool a = i < T.LL;
+    const cx<R> v = src.make(pre.own, sc);
+    const cx<R> h = src.make(pre.hop, sc);
+    cx<R> s3 = src.make(pre.nb[0], sc);
+    s3 = s3 + src.make(pre.nb[1], sc);
+    s3 = s3 + src.make(pre.nb[2], sc);
+    const cx<R> e = ph.value(pre.ph);
+    // e^{+i phi} for M on A sites and M^dag on B sites, e^{-i phi} otherwise
+    const cx<R> f = (a != DAG) ? e : cx<R>{e.re, -e.im};
+    cx<R> o;
+    if (a) {                                  // sgn h - f v
+        const cx<R> fv = cmul(f, v);
+        o = {sgnA * h.re - fv.re, sgnA * h.im - fv.im};
+    } else {                                  // v - sgn f h
+        const cx<R> fh = cmul(f, h);
+        o = {v.re - sgnB * fh.re, v.im - sgnB * fh.im};
+    }
+    return {o.re - T.dk * s3.re, o.im - T.dk * s3.im};
+}
+
 template <typename R, bool DAG, int NB, class Ph, class Src, class Out, class Ctl>
 __global__ void __launch_bounds__(kLinThreads)
 k_lin(const LinTab<R> T, const Ph ph, const Src src, const Out out, const Ctl ctl) {
@@ -970,62 +1052,50 @@ k_lin(const LinTab<R> T, const Ph ph, const Src src, const Out out, const Ctl ct
     const int per_rhs = T.Nt * T.nch;
     const int rhs = u / per_rhs, slot = u - rhs * per_rhs;
     const int t = slot / T.nch, ch = slot - t * T.nch;
+    const int i0 = ch * T.chunk;
+    const int i1 = min(T.V, i0 + T.chunk);
+    const int tp = prev_slice(t, T.Nt), tn = next_slice(t, T.Nt);
+    const long long vb = rhs * T.N;
+    const long long row = (long long)t * T.V;
+    // A sites hop to t+1 (M) or t-1 (M^dag); B sites the other way
+    const long long rowA = (long long)(DAG ? tp : tn) * T.V;
+    const long long rowB = (long long)(DAG ? tn : tp) * T.V;
+    const R sgnA = (DAG ? t == 0 : t == T.Nt - 1) ? (R)-1 : (R)1;
+    const R sgnB = (DAG ? t == T.Nt - 1 : t == 0) ? (R)-1 : (R)1;
+    const long long phB = DAG ? (long long)tn * T.V : row;   // phase slice of the B-site hop
+    const int first = i0 + (int)threadIdx.x;
+    LinPre<R, Src, Ph> pre[NB];
+    typename Out::Pre op[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int i = first + j * kLinThreads;
+        if (i < i1) {
+            lin_fetch<R, DAG>(T, ph, src, i, vb, row, rowA, rowB, phB, pre[j]);
+            op[j] = out.fetch(vb + row + i);
+        }
+    }
     const Scal sc = ctl.begin(rhs, slot, red_lds);
     double acc = 0.0;
     if (sc.open) {
-        const int i0 = ch * T.chunk;
-        const int i1 = min(T.V, i0 + T.chunk);
-        const int tp = prev_slice(t, T.Nt), tn = next_slice(t, T.Nt);
-        const long long vb = rhs * T.N;
-        const long long row = (long long)t * T.V;
-        // A sites hop to t+1 (M) or t-1 (M^dag); B sites the other way
-        const long long rowA = (long long)(DAG ? tp : tn) * T.V;
-        const long long rowB = (long long)(DAG ? tn : tp) * T.V;
-        const R sgnA = (DAG ? t == 0 : t == T.Nt - 1) ? (R)-1 : (R)1;
-        const R sgnB = (DAG ? t == T.Nt - 1 : t == 0) ? (R)-1 : (R)1;
-        const long long phB = DAG ? (long long)tn * T.V : row;   // phase slice of the B-site hop
-        for (int base = i0 + (int)threadIdx.x; base < i1; base += NB * kLinThreads) {
-            LinPre<R, Src, Ph> pre[NB];
-            typename Out::Pre op[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = first + j * kLinThreads;
+            if (i < i1) out.store(vb + row + i, lin_value<R, DAG>(T, ph, src, i, sgnA, sgnB, pre[j], sc), op[j], sc, acc);
+        }
+        for (int base = first + NB * kLinThreads; base < i1; base += NB * kLinThreads) {
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int i = base + j * kLinThreads;
                 if (i < i1) {
-                    int nb[3];
-                    lin_neighbours(i, T.L, T.LL, nb);
-                    const bool a = i < T.LL;
-                    pre[j].own = src.fetch(vb + row + i);
-                    pre[j].hop = src.fetch(vb + (a ? rowA : rowB) + i);
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) pre[j].nb[m] = src.fetch(vb + row + nb[m]);
-                    pre[j].ph = ph.fetch((a ? row : phB) + i);
+                    lin_fetch<R, DAG>(T, ph, src, i, vb, row, rowA, rowB, phB, pre[j]);
                     op[j] = out.fetch(vb + row + i);
                 }
             }
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int i = base + j * kLinThreads;
-                if (i < i1) {
-                    const bool a = i < T.LL;
-                    const cx<R> v = src.make(pre[j].own, sc);
-                    const cx<R> h = src.make(pre[j].hop, sc);
-                    cx<R> s3 = src.make(pre[j].nb[0], sc);
-                    s3 = s3 + src.make(pre[j].nb[1], sc);
-                    s3 = s3 + src.make(pre[j].nb[2], sc);
-                    const cx<R> e = ph.value(pre[j].ph);
-                    // e^{+i phi} for M on A sites and M^dag on B sites, e^{-i phi} otherwise
-                    const cx<R> f = (a != DAG) ? e : cx<R>{e.re, -e.im};
-                    cx<R> o;
-                    if (a) {                                  // sgn h - f v
-                        const cx<R> fv = cmul(f, v);
-                        o = {sgnA * h.re - fv.re, sgnA * h.im - fv.im};
-                    } else {                                  // v - sgn f h
-                        const cx<R> fh = cmul(f, h);
-                        o = {v.re - sgnB * fh.re, v.im - sgnB * fh.im};
-                    }
-                    o = {o.re - T.dk * s3.re, o.im - T.dk * s3.im};
-                    out.store(vb + row + i, o, op[j], sc, acc);
-                }
+                if (i < i1)
+                    out.store(vb + row + i, lin_value<R, DAG>(T, ph, src, i, sgnA, sgnB, pre[j], sc), op[j], sc, acc);
             }
         }
     }
