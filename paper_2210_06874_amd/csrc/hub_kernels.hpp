@@ -4,6 +4,8 @@
 // reliable update and the force, and the deterministic last-block reductions.
 #pragma once
 
+#include <type_traits>
+
 #include "hub_fft.hpp"
 #include "hub_math.hpp"
 
@@ -161,7 +163,8 @@ struct PhAngle {
     __device__ Pre fetch(long long k) const { return phi[k]; }
     __device__ cx<R> value(Pre a) const {
         R s, c;
-        phase_sincos(a, &s, &c);
+        if constexpr (sizeof(R) == sizeof(float)) phase_sincos_fast(a, &s, &c);
+        else phase_sincos(a, &s, &c);
         return {c, s};
     }
 };
@@ -233,7 +236,20 @@ struct SrcSearchNext {           // (r + beta p)_{t+1}                 (CG: M^da
 // ----------------------------------------------------------------------------- epilogues
 // An epilogue functor receives w = (E src)_{t,i} for destination slice t and site i.
 // fetch() issues the loads the epilogue needs, store() writes its outputs and adds its
-// contribution to the block's reduction.
+// contribution to the block's reduction.  early() does the part of the epilogue that
+// does not need w (kernels call it for every entry before store(), as soon as the
+// fetched operands have arrived, so its stores overlap the transform).  Only epilogues
+// that declare kEarly = true have one.
+template <class Epi, class = void>
+struct EpiHasEarly : std::false_type {};
+template <class Epi>
+struct EpiHasEarly<Epi, std::void_t<decltype(Epi::kEarly)>> : std::bool_constant<Epi::kEarly> {};
+
+template <typename R, class Epi>
+__device__ __forceinline__ void epi_early(const Epi& epi, int rhs, int t, int i, typename Epi::Pre& a,
+                                          const OpTab<R>& T, const Scal& sc) {
+    if constexpr (EpiHasEarly<Epi>::value) epi.early(rhs, t, i, a, T, sc);
+}
 template <typename R>
 struct EpiM {                    // out_t = v_t - B_t w
     using Pre = cx<R>;
@@ -300,8 +316,9 @@ struct PreUpdate {
 };
 
 template <typename R>
-struct EpiUpdate {               // CG: q = tv_t - B_t w; p = r + beta p; x += alpha p; r -= alpha q; acc |r|^2
+struct EpiUpdate {               // CG: p = r + beta p; x += alpha p (early); q = tv_t - B_t w; r -= alpha q; acc |r|^2
     using Pre = PreUpdate<R>;
+    static constexpr bool kEarly = true;
     const cx<R>* tv;
     cx<R>* p;
     cx<R>* x;
@@ -310,16 +327,19 @@ struct EpiUpdate {               // CG: q = tv_t - B_t w; p = r + beta p; x += a
         const long long k = rhs * T.N + (long long)t * T.V + i;
         return {tv[k], p[k], x[k], r[k]};
     }
+    __device__ void early(int rhs, int t, int i, Pre& a, const OpTab<R>& T, const Scal& sc) const {
+        const long long k = rhs * T.N + (long long)t * T.V + i;
+        const R b = (R)sc.beta, al = (R)sc.alpha;
+        const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
+        p[k] = pn;
+        x[k] = {a.x.re + al * pn.re, a.x.im + al * pn.im};
+    }
     __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, const Scal& sc,
                           double& acc) const {
         const long long k = rhs * T.N + (long long)t * T.V + i;
-        const R b = (R)sc.beta;
         const R al = (R)sc.alpha;
         const cx<R> q = (t == 0) ? a.tq + w : a.tq - w;
-        const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
         const cx<R> rn = {a.r.re - al * q.re, a.r.im - al * q.im};
-        p[k] = pn;
-        x[k] = {a.x.re + al * pn.re, a.x.im + al * pn.im};
         r[k] = rn;
         acc += (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
     }
@@ -370,7 +390,9 @@ struct EpiForce {                // g_t = -2 B_{t+1} Im(e^{i phi_t} x_t conj(w))
 template <typename R, class Epi>
 __device__ __forceinline__ void epi_apply(const Epi& epi, int rhs, int t, int i, cx<R> w, const OpTab<R>& T,
                                           const Scal& sc, double& acc) {
-    epi.store(rhs, t, i, w, epi.fetch(rhs, t, i, T), T, sc, acc);
+    typename Epi::Pre a = epi.fetch(rhs, t, i, T);
+    epi_early<R>(epi, rhs, t, i, a, T, sc);
+    epi.store(rhs, t, i, w, a, T, sc, acc);
 }
 
 template <typename R, class Src>
@@ -614,17 +636,21 @@ k_fused(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
 // Same layout with L known at compile time (NT threads per workgroup).  The first
 // row stage is fused into the source load and the last inverse row stage into the
 // epilogue, so the slice makes two fewer round trips through LDS.  Every global load
-// is issued early: all source entries and E(k) values before the first butterfly, the
-// epilogue operands one stage before they are needed; each thread keeps them in
-// registers.
+// is issued before the first butterfly (source entries, E(k) values and, when they fit
+// the register budget, the epilogue operands; else those one stage before the
+// epilogue), and the part of the epilogue that does not depend on the transform
+// (early()) runs after the forward row stages, so its stores overlap the rest of it.
 //
 // HALF = true runs two workgroups per slice when there are fewer slices than compute
 // units: both transform the whole source slice forward (the 2 x 2 hopping exponential
 // couples the sublattices), and each mixes, transforms back and writes one sublattice.
 // Three quarters of the arithmetic per workgroup, no communication between them.
+// Register budget per thread for the epilogue operands: held across the whole transform
+// when small (issued with the source loads), else issued one stage before the epilogue.
 template <int BYTES>
-struct EpiPrefetchFits {
-    static constexpr bool value = BYTES <= 400;   // register budget per thread
+struct EpiPrefetch {
+    static constexpr bool early = BYTES <= 192;
+    static constexpr bool late = !early && BYTES <= 400;
 };
 
 template <typename R, int L, int NT, bool HALF, class Src, class Epi, class Ctl>
@@ -639,7 +665,10 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     constexpr int ROUNDS0 = (NT0 + NT - 1) / NT;
     constexpr int ROUNDSO = (NTE + NT - 1) / NT;
     constexpr int ROUNDSE = (LL + NT - 1) / NT;         // momenta per thread in the mix
-    constexpr bool kPreEpi = EpiPrefetchFits<(int)sizeof(typename Epi::Pre) * ROUNDSO * R0>::value;
+    constexpr int kEpiBytes = (int)sizeof(typename Epi::Pre) * ROUNDSO * R0;
+    constexpr bool kPreEarly = EpiPrefetch<kEpiBytes>::early;
+    constexpr bool kPreLate = EpiPrefetch<kEpiBytes>::late;
+    constexpr bool kPreEpi = kPreEarly || kPreLate;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red_lds[64];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
@@ -651,31 +680,45 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     const int off = HALF ? h * LL : 0;                  // first site written
     const int slot = HALF ? 2 * t + h : t;
     const int tid = threadIdx.x;
+    // Every global load is issued before the block learns its CG scalars (the loads do
+    // not depend on them), so the scalar reduction overlaps the fetch.
+    const int ts = src.slice(t, T.Nt);
+    typename Src::Pre pre[ROUNDS0][R0];
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS0; ++rd) {
+        const int task = tid + rd * NT;
+        if (task < NT0) {
+            const int line = task / M0, np = task - line * M0;
+#pragma unroll
+            for (int i = 0; i < R0; ++i) pre[rd][i] = src.fetch(rhs, ts, line * L + np + i * M0, T);
+        }
+    }
+    R ec[ROUNDSE][3];
+#pragma unroll
+    for (int rd = 0; rd < ROUNDSE; ++rd) {
+        const int p = tid + rd * NT;
+        if (p < LL) {
+            ec[rd][0] = T.etab[4 * p];
+            ec[rd][1] = T.etab[4 * p + 1];
+            ec[rd][2] = T.etab[4 * p + 2];
+        }
+    }
+    // epilogue operands, issued with the source (they do not depend on the transform)
+    typename Epi::Pre ep[kPreEpi ? ROUNDSO : 1][kPreEpi ? R0 : 1];
+    if constexpr (kPreEarly) {
+#pragma unroll
+        for (int rd = 0; rd < ROUNDSO; ++rd) {
+            const int task = tid + rd * NT;
+            if (task < NTE) {
+                const int line = task / M0, np = task - line * M0;
+#pragma unroll
+                for (int i = 0; i < R0; ++i) ep[rd][i] = epi.fetch(rhs, t, off + line * L + np + i * M0, T);
+            }
+        }
+    }
     const Scal sc = ctl.begin(rhs, slot, red_lds);
     double acc = 0.0;
     if (sc.open) {
-        const int ts = src.slice(t, T.Nt);
-        // issue every global load of the source and of E(k)
-        typename Src::Pre pre[ROUNDS0][R0];
-#pragma unroll
-        for (int rd = 0; rd < ROUNDS0; ++rd) {
-            const int task = tid + rd * NT;
-            if (task < NT0) {
-                const int line = task / M0, np = task - line * M0;
-#pragma unroll
-                for (int i = 0; i < R0; ++i) pre[rd][i] = src.fetch(rhs, ts, line * L + np + i * M0, T);
-            }
-        }
-        R ec[ROUNDSE][3];
-#pragma unroll
-        for (int rd = 0; rd < ROUNDSE; ++rd) {
-            const int p = tid + rd * NT;
-            if (p < LL) {
-                ec[rd][0] = T.etab[4 * p];
-                ec[rd][1] = T.etab[4 * p + 1];
-                ec[rd][2] = T.etab[4 * p + 2];
-            }
-        }
         for (int i = tid; i < L; i += NT) roots[i] = T.roots[i];
         __syncthreads();
         // row stage 0 (natural-order input) from the prefetched entries
@@ -699,6 +742,17 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
         }
         __syncthreads();
         ct_forward<R, L, 1, P.nst, false, NT>(buf, roots);
+        if constexpr (kPreEarly) {
+#pragma unroll
+            for (int rd = 0; rd < ROUNDSO; ++rd) {
+                const int task = tid + rd * NT;
+                if (task < NTE) {
+                    const int line = task / M0, np = task - line * M0;
+#pragma unroll
+                    for (int i = 0; i < R0; ++i) epi_early<R>(epi, rhs, t, off + line * L + np + i * M0, ep[rd][i], T, sc);
+                }
+            }
+        }
         ct_forward<R, L, 0, P.nst, true, NT>(buf, roots);
         // E(k): A' = c A + sf B,  B' = conj(sf) A + c B
 #pragma unroll
@@ -717,9 +771,7 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
         constexpr int NS = HALF ? 1 : 2;
         cx<R>* own = buf + off;
         ct_inverse<R, L, P.nst - 1, 0, true, NT, NS>(own, roots);
-        // epilogue operands, issued while the last inverse row stages run
-        typename Epi::Pre ep[kPreEpi ? ROUNDSO : 1][kPreEpi ? R0 : 1];
-        if constexpr (kPreEpi) {
+        if constexpr (kPreLate) {
 #pragma unroll
             for (int rd = 0; rd < ROUNDSO; ++rd) {
                 const int task = tid + rd * NT;
@@ -748,8 +800,14 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
                 small_dft_ct<R, R0, true>(x);
 #pragma unroll
                 for (int i = 0; i < R0; ++i) {
-                    if constexpr (kPreEpi) epi.store(rhs, t, off + base + i * M0, x[i], ep[rd][i], T, sc, acc);
-                    else epi_apply(epi, rhs, t, off + base + i * M0, x[i], T, sc, acc);
+                    if constexpr (kPreEarly) {
+                        epi.store(rhs, t, off + base + i * M0, x[i], ep[rd][i], T, sc, acc);
+                    } else if constexpr (kPreLate) {
+                        epi_early<R>(epi, rhs, t, off + base + i * M0, ep[rd][i], T, sc);
+                        epi.store(rhs, t, off + base + i * M0, x[i], ep[rd][i], T, sc, acc);
+                    } else {
+                        epi_apply(epi, rhs, t, off + base + i * M0, x[i], T, sc, acc);
+                    }
                 }
             }
         }

@@ -1,9 +1,9 @@
 // Device math helpers: sin and cos of the Hubbard-field phases.
 //
-// Cody-Waite argument reduction x = k (pi/2) + r, |r| <= pi/4, with pi/2 split into
-// three parts whose leading parts have trailing zero bits (so k * part is exact for
-// the |x| bound below), followed by the Taylor series of sin and cos truncated where
-// the remainder drops below half an ulp on [-pi/4, pi/4].  Arguments outside the
+// FP64: Cody-Waite argument reduction x = k (pi/2) + r, |r| <= pi/4, with pi/2 split
+// into three parts whose leading parts have trailing zero bits (so k * part is exact
+// for the |x| bound below), followed by the Taylor series of sin and cos truncated
+// where the remainder drops below half an ulp on [-pi/4, pi/4].  Arguments outside the
 // bound (and NaN/Inf) take the library routine.
 #pragma once
 
@@ -49,34 +49,19 @@ __device__ __forceinline__ void phase_sincos(double x, double* s, double* c) {
     *c = ((q + 1) & 2) ? -cc : cc;
 }
 
-__device__ __forceinline__ void phase_sincos(float x, float* s, float* c) {
+// FP32 phases for the single-precision operators: the argument is reduced to at most
+// half a revolution (one product, a rounding and an fma) and the CDNA transcendental
+// units evaluate sin(2 pi f) and cos(2 pi f).  Accurate to a few ulp of the FP32
+// operator's inputs, which is all the single-precision path needs.
+__device__ __forceinline__ void phase_sincos_fast(float x, float* s, float* c) {
     if (!(fabsf(x) < 6000.0f)) {
         sincosf(x, s, c);
         return;
     }
-    const float k = rintf(x * 0.63661977f);
-    float r = fmaf(-k, 1.57080078125f, x);                     // pi/2 = P1 + P2 + P3 (12-bit leading parts)
-    r = fmaf(-k, -4.4535846e-06f, r);
-    r = fmaf(-k, -8.7055158e-10f, r);
-    const float z = r * r;
-    float qs = -1.0f / 39916800.0f;                            // sin r = r + r z Q(z), through r^11
-    qs = fmaf(qs, z, 1.0f / 362880.0f);
-    qs = fmaf(qs, z, -1.0f / 5040.0f);
-    qs = fmaf(qs, z, 1.0f / 120.0f);
-    qs = fmaf(qs, z, -1.0f / 6.0f);
-    const float sr = fmaf(r * z, qs, r);
-    float pc = 1.0f / 479001600.0f;                            // cos r = 1 + z P(z), through r^12
-    pc = fmaf(pc, z, -1.0f / 3628800.0f);
-    pc = fmaf(pc, z, 1.0f / 40320.0f);
-    pc = fmaf(pc, z, -1.0f / 720.0f);
-    pc = fmaf(pc, z, 1.0f / 24.0f);
-    pc = fmaf(pc, z, -0.5f);
-    const float cr = fmaf(pc, z, 1.0f);
-    const int q = (int)k & 3;
-    const float ss = (q & 1) ? cr : sr;
-    const float cc = (q & 1) ? sr : cr;
-    *s = (q & 2) ? -ss : ss;
-    *c = ((q + 1) & 2) ? -cc : cc;
+    constexpr float kInv2Pi = 0.15915494309189535f;
+    const float f = fmaf(x, kInv2Pi, -rintf(x * kInv2Pi));   // revolutions, |f| <= 1/2
+    *s = __builtin_amdgcn_sinf(f);
+    *c = __builtin_amdgcn_cosf(f);
 }
 
 }  // namespace hub
