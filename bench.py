@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -34,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "M-applications/s & s per HMC force, L=51 Nt=128, FP32-mixed vs FP64 @1e-10 res"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_M_c64_L51_Nt128.txt")
 TRAFFIC_FILE_LIN = os.path.join(ROOT, "profiles", "traffic_apply_M_c64_linear_L51_Nt128.txt")
@@ -126,6 +128,7 @@ def cpu_baseline(w, phi, chi, budget_s: float = 15.0):
     blas = threadpoolctl.threadpool_info()
     # scipy's sparse products in expm_multiply run on one thread; numpy BLAS is not used here
     return {"value": n / dt, "unit": "M-applications/s", "cores": 1, "kind": "oracle",
+            "s_per_cg_iteration": 2.0 * dt / n,
             "sample": f"{n} alternating M / M^dag applications at L=51 Nt=128 (Krylov exp-multiply "
                       f"route, FP64), {dt:.1f} s; host has {os.cpu_count()} cores, BLAS "
                       f"{blas[0]['internal_api'] if blas else 'none'} unused"}
@@ -258,11 +261,19 @@ def main() -> int:
     alg32 = 20.0 * w.N          # read v (8N) + phi (4N), write out (8N)
     alg64 = 40.0 * w.N
     traffic = read_traffic(TRAFFIC_FILE)
+    # the FFT convention 5 n log2 n flops per complex transform of n points: four L x L
+    # transforms per slice (two sublattices, forward and inverse)
+    fft_flops = w.Nt * 4 * 5.0 * w.L ** 2 * math.log2(w.L ** 2)
     roof = {"bound": "hbm", "achieved": alg32 / t_k32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": alg32 / t_k32 / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "hub_apply_M_c64 (k_fused_ct<float, 51, ...> two workgroups per slice)",
             "avg_launch_us": t_k32 * 1e6, "avg_launch_us_python_loop": t_loop32 * 1e6,
-            "alg_bytes_per_launch": alg32, "timing": "HIP graph of 50 launches, events on its stream"}
+            "alg_bytes_per_launch": alg32, "site_slices_per_s": w.N / t_k32,
+            "alu": {"flops_per_launch": fft_flops, "achieved_tflops": fft_flops / t_k32 / 1e12,
+                    "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+                    "frac": fft_flops / t_k32 / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                    "convention": "5 n log2 n per complex transform, 4 transforms of L^2 points per slice"},
+            "timing": "HIP graph of 50 launches, events on its stream"}
     roof64 = {"achieved": alg64 / t_k64 / 1e9, "frac": alg64 / t_k64 / 1e9 / HBM_PEAK_GBS,
               "avg_launch_us": t_k64 * 1e6, "alg_bytes_per_launch": alg64}
 

@@ -4,8 +4,9 @@ import pytest
 import torch
 
 import oracle as O
-from workloads import TINY, SMALL, DIFF_SUB, Lattice, draw_inputs, draw_complex
+from workloads import TINY, SMALL, DIFF_SUB, PREC, STRESS, Lattice, draw_inputs, draw_complex
 from gpu_common import dev, to_dev, to_np, oracle_op
+import closed_forms as CF
 
 pytestmark = pytest.mark.gpu
 
@@ -159,3 +160,32 @@ def test_cg_error_paths():
     assert e.value.status == HUB_ERR_ARG
     with pytest.raises(HubError):
         hub.cg_solve(to_dev(phi), to_dev(np.concatenate([chi, chi])), tol=1e-10)   # nrhs > nrhs_max
+
+
+def _free_cond(w):
+    """cond(M M^dag) at phi = 0 from the closed-form spectrum |1 - e^{-i omega} e^{delta eps}|^2."""
+    om = (2 * np.arange(w.Nt) + 1) * np.pi / w.Nt
+    a = np.abs(CF.f_of_k(w.L)).ravel()
+    eps = np.concatenate([a, -a]) * w.kappa
+    lam2 = np.abs(1 - np.exp(-1j * om[:, None]) * np.exp(w.delta * eps[None, :])) ** 2
+    return lam2.max() / lam2.min()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("w", [PREC, STRESS], ids=lambda w: w.name)
+def test_cg_free_plane_wave_at_scale(w, prec):
+    """phi = 0, chi a plane wave: x = chi / |1 - e^{-i omega} e^{delta eps}|^2 exactly (P2 through
+    the solver); the returned x is within cond * tol of it."""
+    print(f"[case] cg plane wave {prec} {w.name}", flush=True)
+    hub = _hub(w)
+    phi = torch.zeros((w.Nt, w.V), dtype=torch.float64, device=dev())
+    cond = _free_cond(w)
+    for (n, m1, m2, band) in [(0, 1, 2, 1), (w.Nt // 2, w.L // 3, 2 * w.L // 3, -1)]:
+        v, eps, om = CF.plane_wave(w.L, w.Nt, n, m1, m2, band)
+        lam = CF.free_M_eigenvalue(eps, om, w.delta)
+        res = hub.cg_solve(phi, to_dev(v), tol=1e-10, prec=prec)
+        assert res.converged and res.true_rel_res[0] <= 1e-10
+        x = to_np(res.x)
+        ref = v / abs(lam) ** 2
+        err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+        assert err <= 2 * cond * 1e-10, (n, m1, m2, err, cond)
