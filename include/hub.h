@@ -34,8 +34,9 @@
  *
  * Ownership: every array argument is a DEVICE pointer on the context's device,
  * owned by the caller; the library keeps no pointer after a call returns.  The
- * context owns its tables and workspace (allocated by hub_create / lazily by
- * the first hub_cg_solve, freed by hub_destroy).
+ * context owns its tables and workspace: hub_create allocates the tables, the
+ * reduction partials and the operator scratch, the first hub_cg_solve the solver
+ * vectors; nothing else allocates; hub_destroy frees all of it.
  *
  * Streams: every call enqueues its work on `stream` (a hipStream_t; NULL means
  * the default stream) and returns without synchronising, except hub_cg_solve,

@@ -88,7 +88,12 @@ void allow_lds(K kern, size_t bytes) {
 
 // Which operator kernel runs for nrhs right-hand sides, and how many reduction slots
 // (blocks per right-hand side) it has.
-enum class OpKind { Generic, Whole51, Half51, Split, Linear };
+enum class OpKind { Generic, Whole51, Half51, Split, Linear, Sub102 };
+
+#ifndef HUB_THREADS_SUB
+#define HUB_THREADS_SUB 512
+#endif
+constexpr int kThreadsSub = HUB_THREADS_SUB;   // workgroup size of the sublattice-at-a-time kernel
 
 #ifndef HUB_LIN_BATCH
 #define HUB_LIN_BATCH 3
@@ -111,15 +116,22 @@ int lin_nch(const hub_ctx* c, int nrhs) {
     return std::max(1, n);
 }
 
+// R: the precision of the launch (FP32 slices at L = 102 exceed LDS but one sublattice
+// fits; FP64 ones take the split path).
+template <typename R>
 OpKind op_kind(const hub_ctx* c, int nrhs) {
     if (c->form == HUB_FORM_LINEAR) return OpKind::Linear;
-    if (c->path == HUB_PATH_SPLIT) return OpKind::Split;
+    if (c->path == HUB_PATH_SPLIT) {
+        if (!c->split_forced && c->specialized && c->L == 102 && sizeof(R) == sizeof(float)) return OpKind::Sub102;
+        return OpKind::Split;
+    }
     if (c->L == 51 && c->specialized) return nrhs * c->Nt < kHalfBelow ? OpKind::Half51 : OpKind::Whole51;
     return OpKind::Generic;
 }
 
+template <typename R>
 int op_slots(const hub_ctx* c, int nrhs) {
-    switch (op_kind(c, nrhs)) {
+    switch (op_kind<R>(c, nrhs)) {
         case OpKind::Half51: return 2 * c->Nt;
         case OpKind::Split: return 2 * c->Nt * split_geom(c->L).nrb;
         case OpKind::Linear: return c->Nt * lin_nch(c, nrhs);
@@ -131,10 +143,20 @@ int op_slots(const hub_ctx* c, int nrhs) {
 template <typename R, class Src, class Epi, class Ctl>
 hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ctl& ctl_in, hipStream_t st) {
     const OpTab<R> T = op_tab<R>(c);
-    const OpKind kind = op_kind(c, nrhs);
-    const Ctl ctl = ctl_in.with_slots(op_slots(c, nrhs));
+    const OpKind kind = op_kind<R>(c, nrhs);
+    const Ctl ctl = ctl_in.with_slots(op_slots<R>(c, nrhs));
     const size_t lds = fused_lds<R>(c);
     switch (kind) {
+        case OpKind::Sub102: {
+            if constexpr (sizeof(R) == sizeof(float)) {
+                auto kern = k_fused_sub<R, 102, kThreadsSub, Src, Epi, Ctl>;
+                const size_t lds_sub = (size_t)(c->L * c->L + c->L) * sizeof(cx<R>);
+                allow_lds(kern, lds_sub);
+                hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreadsSub), lds_sub, st, T, src, epi, ctl);
+                return launch_check("k_fused_sub<102>");
+            }
+            return fail(HUB_ERR_ARG, "internal: sublattice kernel is FP32 only");
+        }
         case OpKind::Half51: {
             auto kern = k_fused_ct<R, 51, kThreads51, true, Src, Epi, Ctl>;
             allow_lds(kern, lds);
@@ -190,7 +212,7 @@ template <typename R, bool DAG, class Ph, class Src, class Out, class Ctl>
 hub_status run_lin(hub_ctx* c, int nrhs, const Ph& ph, const Src& src, const Out& out, const Ctl& ctl_in,
                    hipStream_t st) {
     const LinTab<R> T = lin_tab<R>(c, nrhs);
-    const Ctl ctl = ctl_in.with_slots(op_slots(c, nrhs));
+    const Ctl ctl = ctl_in.with_slots(op_slots<R>(c, nrhs));
     hipLaunchKernelGGL((k_lin<R, DAG, kLinBatch, Ph, Src, Out, Ctl>), dim3(nrhs * c->Nt * T.nch),
                        dim3(kLinThreads), 0, st, T, ph, src, out, ctl);
     return launch_check(DAG ? "k_lin<dag>" : "k_lin");
@@ -292,7 +314,7 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     const bool lin = c->form == HUB_FORM_LINEAR;
 
     // ||r||^2 partials of iterations i, i-1, i+1 rotate through three buffers (index i mod 3)
-    const int slots = op_slots(c, nrhs);
+    const int slots = op_slots<Rlo>(c, nrhs);   // the iteration kernels' reduction slots
     auto pr = [&](long long i) { return c->cg_pr + (size_t)(i % 3) * nrhs * slots; };
     double* pt = c->cg_pt;
 
@@ -439,6 +461,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
         return bail(fail(HUB_ERR_ARG, "fused path needs %d B of LDS, device has %d", c->lds_fused64, c->max_lds));
     c->path = (prm->path == HUB_PATH_SPLIT || (prm->path == HUB_PATH_AUTO && !fits)) ? HUB_PATH_SPLIT
                                                                                       : HUB_PATH_FUSED;
+    c->split_forced = prm->path == HUB_PATH_SPLIT;
 
     std::vector<double> roots, etab;
     if (!lin) build_tables(plan, c->delta * c->kappa, c->delta * prm->mu, roots, etab);
@@ -471,6 +494,9 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     CREATE_OR_BAIL(hipMalloc(&c->red_out, 8 * sizeof(double)));
     if (c->path == HUB_PATH_SPLIT && !lin)
         CREATE_OR_BAIL(hipMalloc(&c->split_w, (size_t)c->nrhs_max * c->N * sizeof(cx<double>)));
+    // per-right-hand-side forces before their sum (exponential form, nrhs > 1)
+    if (c->nrhs_max > 1 && !lin)
+        CREATE_OR_BAIL(hipMalloc(&c->force_tmp, (size_t)c->nrhs_max * c->N * sizeof(double)));
     CREATE_OR_BAIL(hipStreamSynchronize(st));   // host vectors above go out of scope
 #undef CREATE_OR_BAIL
     *out = c;
@@ -535,7 +561,6 @@ hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, in
     }
     if (nrhs == 1)
         return run_op<double>(c, 1, SrcNext<double>{xv}, EpiForce{xv, {phi}, g, 0}, CtlPlain{}, st);
-    if (!c->force_tmp) HIP_OR_FAIL(hipMalloc(&c->force_tmp, (size_t)c->nrhs_max * c->N * sizeof(double)));
     s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, {phi}, c->force_tmp, c->N}, CtlPlain{}, st);
     if (s != HUB_OK) return s;
     hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, c->force_tmp, g, c->N, nrhs);

@@ -41,6 +41,7 @@ struct hub_ctx {
     int path = HUB_PATH_FUSED;
     int form = HUB_FORM_EXP;
     bool specialized = true;         // use a compile-time-L kernel when one exists
+    bool split_forced = false;       // HUB_PATH_SPLIT requested: no fused kernel of any kind
     int lds_fused64 = 0, lds_fused32 = 0;
     int max_lds = 0;
     hub::FftPlan plan{};
@@ -74,5 +75,5 @@ struct hub_ctx {
     double* cg_pr = nullptr;             // ||r||^2 partials, [3][nrhs_max][max_partials]
     double* cg_pt = nullptr;             // ||M^dag p||^2 partials, [nrhs_max][max_partials]
     hub::CgScalars* scal_host = nullptr; // pinned host mirror
-    double* force_tmp = nullptr;         // [nrhs_max][N] doubles, per-rhs force before summation
+    double* force_tmp = nullptr;         // [nrhs_max][N] doubles, per-rhs force before summation (hub_create)
 };

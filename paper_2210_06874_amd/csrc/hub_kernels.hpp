@@ -815,6 +815,133 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
 }
 
+// One workgroup per (right-hand side, slice) for slices larger than LDS whose single
+// sublattice fits (FP32 at L = 102: 84 KB of the slice's 167 KB).  Sublattice A is
+// transformed forward in LDS and its spectrum parked in registers (each thread keeps
+// the momenta it will mix); then B is transformed in the same LDS, the 2 x 2 E(k) mix
+// pairs each register-held A entry with the LDS-held B entry, B is transformed back
+// and written, then the mixed A spectrum returns to LDS and is transformed back and
+// written.  Two forward and two inverse sublattice transforms per slice, none repeated.
+// The loads of B's source are issued before A's column stages, so they arrive while those run.
+template <typename R, int L, int NT, class Src, class Epi, class Ctl>
+__global__ void __launch_bounds__(NT)
+k_fused_sub(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
+    constexpr CPlan P = make_cplan(L);
+    static_assert(P.nst >= 2, "needs a row stage besides the fused one");
+    constexpr int LL = L * L;
+    constexpr int R0 = P.radix[0], M0 = L / R0;
+    constexpr int NTS = L * M0;                         // stage-0 tasks of one sublattice
+    constexpr int ROUNDS = (NTS + NT - 1) / NT;
+    constexpr int NP = (LL + NT - 1) / NT;              // momenta per thread in the mix
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    cx<R>* roots = buf + LL;
+    const int u = xcd_linear(blockIdx.x, gridDim.x);
+    const int rhs = u / T.Nt, t = u - rhs * T.Nt;
+    const int tid = threadIdx.x;
+    const int ts = src.slice(t, T.Nt);
+    typename Src::Pre pre[ROUNDS][R0];
+    auto fetch_sub = [&](int s) {
+#pragma unroll
+        for (int rd = 0; rd < ROUNDS; ++rd) {
+            const int task = tid + rd * NT;
+            if (task < NTS) {
+                const int line = task / M0, np = task - line * M0;
+#pragma unroll
+                for (int i = 0; i < R0; ++i) pre[rd][i] = src.fetch(rhs, ts, s * LL + line * L + np + i * M0, T);
+            }
+        }
+    };
+    fetch_sub(0);
+    const Scal sc = ctl.begin(rhs, t, red_lds);
+    double acc = 0.0;
+    if (sc.open) {
+        for (int i = tid; i < L; i += NT) roots[i] = T.roots[i];
+        cx<R> ahat[NP];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            __syncthreads();
+            // row stage 0 of sublattice s (natural-order input) from the fetched entries
+#pragma unroll
+            for (int rd = 0; rd < ROUNDS; ++rd) {
+                const int task = tid + rd * NT;
+                if (task < NTS) {
+                    const int line = task / M0, np = task - line * M0;
+                    const int base = line * L + np;
+                    cx<R> x[R0];
+#pragma unroll
+                    for (int i = 0; i < R0; ++i) x[i] = src.make(pre[rd][i], sc);
+                    small_dft_ct<R, R0, false>(x);
+                    if constexpr (M0 > 1) {
+#pragma unroll
+                        for (int k = 1; k < R0; ++k) x[k] = cmul(x[k], roots[np * k]);
+                    }
+#pragma unroll
+                    for (int i = 0; i < R0; ++i) buf[base + i * M0] = x[i];
+                }
+            }
+            __syncthreads();
+            ct_forward<R, L, 1, P.nst, false, NT, 1>(buf, roots);
+            if (s == 0) fetch_sub(1);     // B's source arrives during A's column stages
+            ct_forward<R, L, 0, P.nst, true, NT, 1>(buf, roots);
+            if (s == 0) {
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    const int p = tid + j * NT;
+                    if (p < LL) ahat[j] = buf[p];
+                }
+            }
+        }
+        // E(k): A' = c A + sf B (kept in registers),  B' = conj(sf) A + c B (in LDS)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int p = tid + j * NT;
+            if (p < LL) {
+                const R c = T.etab[4 * p], sr = T.etab[4 * p + 1], si = T.etab[4 * p + 2];
+                const cx<R> a = ahat[j], b = buf[p];
+                ahat[j] = {c * a.re + sr * b.re - si * b.im, c * a.im + sr * b.im + si * b.re};
+                buf[p] = {c * b.re + sr * a.re + si * a.im, c * b.im + sr * a.im - si * a.re};
+            }
+        }
+#pragma unroll
+        for (int s = 1; s >= 0; --s) {
+            if (s == 0) {
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    const int p = tid + j * NT;
+                    if (p < LL) buf[p] = ahat[j];
+                }
+            }
+            __syncthreads();
+            ct_inverse<R, L, P.nst - 1, 0, true, NT, 1>(buf, roots);
+            ct_inverse<R, L, P.nst - 1, 1, false, NT, 1>(buf, roots);
+            // row stage 0 inverse (natural-order output) straight into the epilogue; a few
+            // rounds at a time (the ahat registers are still live)
+#pragma unroll 2
+            for (int rd = 0; rd < ROUNDS; ++rd) {
+                const int task = tid + rd * NT;
+                if (task < NTS) {
+                    const int line = task / M0, np = task - line * M0;
+                    const int base = line * L + np;
+                    cx<R> x[R0];
+#pragma unroll
+                    for (int k = 0; k < R0; ++k) x[k] = buf[base + k * M0];
+                    if constexpr (M0 > 1) {
+#pragma unroll
+                        for (int k = 1; k < R0; ++k) x[k] = cmulc(x[k], roots[np * k]);
+                    }
+                    small_dft_ct<R, R0, true>(x);
+#pragma unroll
+                    for (int i = 0; i < R0; ++i) epi_apply(epi, rhs, t, s * LL + base + i * M0, x[i], T, sc, acc);
+                }
+            }
+        }
+    }
+    if constexpr (Ctl::kEnd) ctl.end(acc, rhs, t, sc, red_lds);
+}
+
 // e^{i phi} as a table, evaluated in FP64 and rounded once to R
 template <typename R>
 __global__ void __launch_bounds__(kThreads)

@@ -199,3 +199,19 @@ def test_apply_with_chemical_potential(mu):
         assert_close_elementwise(to_np(hub.apply_M(to_dev(phi), to_dev(v))), op.apply_M(phi, v), RTOL64, "M")
         assert_close_elementwise(to_np(hub.apply_Mdag(to_dev(phi), to_dev(v))), op.apply_Mdag(phi, v), RTOL64,
                                  "Mdag")
+
+
+@pytest.mark.parametrize("dag", [False, True])
+def test_sublattice_and_split_kernels_agree(dag):
+    """L = 102 in FP32: the one-workgroup-per-slice kernel that keeps one sublattice's
+    spectrum in registers against the three-kernel split path (both against the oracle on
+    sampled slices in test_apply_stress_workload_sampled)."""
+    w = STRESS
+    print(f"[case] sublattice vs split dag={dag}", flush=True)
+    phi, v = draw_inputs(w, seed=18, nrhs=2)
+    P32, V32 = to_dev(phi.astype(np.float32)), to_dev(v.astype(np.complex64))
+    a = _hub(w, "auto", nrhs=2)
+    b = _hub(w, "split", nrhs=2)
+    fa = a.apply_Mdag_c64 if dag else a.apply_M_c64
+    fb = b.apply_Mdag_c64 if dag else b.apply_M_c64
+    assert_close_elementwise(to_np(fa(P32, V32)), to_np(fb(P32, V32)), 4e-6, "sub vs split")
