@@ -96,6 +96,10 @@ typedef struct {
     int32_t reliable_every; /* FP64 residual recomputation every this many iterations, >= 1     */
     int32_t prec;           /* hub_prec: FP64 throughout, or FP32 inner iterations               */
     int32_t use_x0;         /* 1: x holds the initial guess on entry; 0: start from x = 0       */
+    int32_t stall_updates;  /* > 0: stop with HUB_ERR_NOCONV once, for every unfinished
+                               right-hand side, this many consecutive reliable updates found the
+                               iterated residual below tol but no 1 % gain on the best true
+                               residual (the attainable-accuracy floor); 0: off               */
 } hub_cg_opts;
 
 typedef struct {
@@ -138,7 +142,8 @@ hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, vo
  * always judged on the true FP64 residual.
  * chi, x: complex128 [nrhs][Nt][V], must not overlap.  info_host: nrhs entries
  * in HOST memory (may be NULL).  Returns HUB_ERR_NOCONV (x = last FP64 iterate,
- * info filled) or HUB_ERR_NONFINITE when the iteration breaks down. */
+ * info filled) at max_iter or on stagnation (opts->stall_updates), or
+ * HUB_ERR_NONFINITE when the iteration breaks down. */
 hub_status hub_cg_solve(hub_ctx* ctx, const double* phi, const void* chi, void* x, int32_t nrhs,
                         const hub_cg_opts* opts, hub_cg_info* info_host, void* stream);
 

@@ -131,8 +131,13 @@ class Hubbard:
 
     # ------------------------------------------------------------------ solver, action, force
     def cg_solve(self, phi, chi, tol: float = 1e-10, max_iter: int = 100000, prec: str = "fp64",
-                 reliable_every: int = 50, x0=None, raise_on_error: bool = True) -> CgResult:
-        """x = (M M^dag)^{-1} chi by conjugate gradients (true FP64 residual <= tol)."""
+                 reliable_every: int = 50, x0=None, raise_on_error: bool = True,
+                 stall_updates: int = 0) -> CgResult:
+        """x = (M M^dag)^{-1} chi by conjugate gradients (true FP64 residual <= tol).
+
+        stall_updates > 0 ends a solve stuck at its attainable accuracy early (HUB_ERR_NOCONV):
+        after that many consecutive reliable updates that found the iterated residual below tol
+        but no 1 % gain on the best true residual."""
         phi = self._phi(phi)
         chi3, nrhs = self._vec(chi, name="chi")
         if x0 is None:
@@ -141,7 +146,8 @@ class Hubbard:
         else:
             x, _ = self._vec(x0.clone(), name="x0")
             use_x0 = 1
-        opts = _lib.HubCgOpts(float(tol), int(max_iter), int(reliable_every), _PREC[prec], use_x0)
+        opts = _lib.HubCgOpts(float(tol), int(max_iter), int(reliable_every), _PREC[prec], use_x0,
+                              int(stall_updates))
         info = (_lib.HubCgInfo * nrhs)()
         with torch.cuda.device(self.device):
             st = self.lib.hub_cg_solve(self._h, self._p(phi), self._p(chi3), self._p(x), nrhs,

@@ -357,19 +357,44 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     hub_status result = HUB_OK;
     long long it = 0;
     const int every = o.reliable_every;
+    // stagnation watch: per rhs, the best true ||r||^2 seen and the consecutive stalled updates
+    std::vector<double> best(nrhs, HUGE_VAL);
+    std::vector<int> seen(nrhs, 0), stalled(nrhs, 0);
     for (;;) {
         HIP_OR_FAIL(hipMemcpyAsync(c->scal_host, sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, st));
         HIP_OR_FAIL(hipStreamSynchronize(st));
-        bool all_done = true, bad = false;
+        bool all_done = true, bad = false, all_stalled = true;
         for (int r = 0; r < nrhs; ++r) {
-            all_done &= c->scal_host[r].done != 0;
-            bad |= c->scal_host[r].nonfinite != 0;
+            const CgScalars& h = c->scal_host[r];
+            all_done &= h.done != 0;
+            bad |= h.nonfinite != 0;
+            if (h.done) continue;
+            if (h.reliable > seen[r]) {
+                // a stalled update: the iterated residual had met tol, the true one made no
+                // 1 % progress (the attainable-accuracy floor); slow progress is not a stall
+                seen[r] = h.reliable;
+                if (h.true_rr < 0.98 * best[r]) {
+                    best[r] = h.true_rr;
+                    stalled[r] = 0;
+                } else if (h.rec_rr <= h.tol2) {
+                    stalled[r] += 1;
+                } else {
+                    stalled[r] = 0;
+                }
+            }
+            all_stalled &= stalled[r] >= o.stall_updates;
         }
         if (bad) {
             result = fail(HUB_ERR_NONFINITE, "CG breakdown: non-finite or non-positive scalar");
             break;
         }
         if (all_done) break;
+        if (o.stall_updates > 0 && all_stalled) {
+            result = fail(HUB_ERR_NOCONV, "CG stagnated at its attainable accuracy: %d reliable updates "
+                                          "without progress (tol=%g)",
+                          o.stall_updates, o.tol);
+            break;
+        }
         if (it >= o.max_iter) {
             result = fail(HUB_ERR_NOCONV, "CG did not reach tol=%g within max_iter=%d", o.tol, o.max_iter);
             break;
@@ -538,6 +563,7 @@ hub_status hub_cg_solve(hub_ctx* c, const double* phi, const void* chi, void* x,
     if (opts->reliable_every < 1) return fail(HUB_ERR_ARG, "reliable_every must be >= 1");
     if (opts->prec != HUB_PREC_FP64 && opts->prec != HUB_PREC_MIXED) return fail(HUB_ERR_ARG, "bad prec");
     if (opts->use_x0 != 0 && opts->use_x0 != 1) return fail(HUB_ERR_ARG, "use_x0 must be 0 or 1");
+    if (opts->stall_updates < 0) return fail(HUB_ERR_ARG, "stall_updates must be >= 0");
     s = ensure_cg_workspace(c);
     if (s != HUB_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);

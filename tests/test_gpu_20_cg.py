@@ -89,6 +89,16 @@ def test_cg_small_iid_meets_attainable_accuracy():
     assert hard.status == HUB_ERR_NOCONV and 0 < hard.iters[0] <= 12000
     assert hard.reliable_updates[0] >= 12000 // 50
     assert hard.true_rel_res[0] <= 1e-8
+    # stagnation detection ends the same unattainable solve early, at the floor
+    st = hub.cg_solve(to_dev(phi), to_dev(chi), tol=min(1e-12, floor / 100), prec="fp64",
+                      max_iter=100000, raise_on_error=False, stall_updates=4)
+    print(f"    stalled after {st.iters[0]} iterations, {st.reliable_updates[0]} updates, "
+          f"true {st.true_rel_res[0]:.2e}", flush=True)
+    assert st.status == HUB_ERR_NOCONV and st.iters[0] < 100000
+    assert st.true_rel_res[0] <= 1e-8
+    # and never fires on a solve that converges
+    ok = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-9, prec="mixed", max_iter=40000, stall_updates=4)
+    assert ok.converged
 
 
 def test_cg_multiple_rhs_equal_single_solves():
@@ -160,6 +170,9 @@ def test_cg_error_paths():
     assert e.value.status == HUB_ERR_ARG
     with pytest.raises(HubError):
         hub.cg_solve(to_dev(phi), to_dev(np.concatenate([chi, chi])), tol=1e-10)   # nrhs > nrhs_max
+    with pytest.raises(HubError) as e:
+        hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-10, stall_updates=-1)
+    assert e.value.status == HUB_ERR_ARG
 
 
 def _free_cond(w):

@@ -57,6 +57,9 @@ def test_autograd_backward_is_force():
     hub = _hub(w)
     P = to_dev(phi).requires_grad_(True)
     S = PseudofermionAction.apply(P, to_dev(chi), hub, 1e-12)
+    # what backward keeps: the field and the solution, nothing per slice
+    saved = S.grad_fn.saved_tensors
+    assert [tuple(t.shape) for t in saved] == [(w.Nt, w.V), (1, w.Nt, w.V)]
     S.backward()
     res = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-12)
     g = hub.force(to_dev(phi), res.x)
