@@ -118,7 +118,8 @@ hub_status hub_create(const hub_params* params, void* stream, hub_ctx** out);
 void hub_destroy(hub_ctx* ctx);
 
 /* out = M[phi] in  (Sec. 2, eq. "ferm_op", in the context's form), FP64.
- * in and out: complex128 [nrhs][Nt][V]; must not overlap.  1 <= nrhs <= nrhs_max. */
+ * in and out: complex128 [nrhs][Nt][V]; out may overlap neither in nor phi (HUB_ERR_ARG).
+ * 1 <= nrhs <= nrhs_max. */
 hub_status hub_apply_M(hub_ctx* ctx, const double* phi, const void* in, void* out,
                        int32_t nrhs, void* stream);
 
@@ -140,7 +141,7 @@ hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, vo
  * reliable_every iterations (or as soon as the iterated residual meets tol) the
  * FP64 solution is updated and the FP64 residual recomputed.  Convergence is
  * always judged on the true FP64 residual.
- * chi, x: complex128 [nrhs][Nt][V], must not overlap.  info_host: nrhs entries
+ * chi, x: complex128 [nrhs][Nt][V]; x may overlap neither chi nor phi.  info_host: nrhs entries
  * in HOST memory (may be NULL).  Returns HUB_ERR_NOCONV (x = last FP64 iterate,
  * info filled) at max_iter or on stagnation (opts->stall_updates), or
  * HUB_ERR_NONFINITE when the iteration breaks down. */
@@ -153,7 +154,8 @@ hub_status hub_cg_solve(hub_ctx* ctx, const double* phi, const void* chi, void* 
  * HUB_FORM_LINEAR, with y_r = M^dag x_r:
  *     A sites: dSdphi[t][z] = sum_r -2 Im( e^{i phi_{t,z}} conj(x_{r,t,z}) y_{r,t,z} )
  *     B sites: dSdphi[t][z] = sum_r 2 B_t Im( e^{-i phi_{t,z}} conj(x_{r,t,z}) y_{r,t-1,z} ).
- * dSdphi (double [Nt][V]) is overwritten.  The Gaussian term phi/(delta U) is the caller's. */
+ * dSdphi (double [Nt][V]) is overwritten and may overlap neither x nor phi.  The Gaussian
+ * term phi/(delta U) is the caller's. */
 hub_status hub_force(hub_ctx* ctx, const double* phi, const void* x, double* dSdphi,
                      int32_t nrhs, void* stream);
 

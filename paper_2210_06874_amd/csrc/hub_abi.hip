@@ -72,18 +72,21 @@ OpTab<float> op_tab<float>(const hub_ctx* c) {
     return {reinterpret_cast<const cx<float>*>(c->roots32), c->etab32, c->plan, c->L, c->V, c->Nt, c->N};
 }
 
-// Raise a kernel's dynamic-LDS limit once per kernel (and again for a larger size).
+// Raise a kernel's dynamic-LDS limit once per (device, kernel), and again for a larger
+// size.  A failure here surfaces as a launch error of that kernel.
 template <typename K>
 void allow_lds(K kern, size_t bytes) {
     static std::mutex mu;
-    static std::unordered_map<const void*, size_t> granted;
+    static std::unordered_map<const void*, size_t> granted[64];
     if (bytes <= 65536) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
     const void* key = reinterpret_cast<const void*>(kern);
     std::lock_guard<std::mutex> lock(mu);
-    auto it = granted.find(key);
-    if (it != granted.end() && it->second >= bytes) return;
+    auto it = granted[dev].find(key);
+    if (it != granted[dev].end() && it->second >= bytes) return;
     if (hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
-        granted[key] = bytes;
+        granted[dev][key] = bytes;
 }
 
 // Which operator kernel runs for nrhs right-hand sides, and how many reduction slots
@@ -225,9 +228,10 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 }
 
 // in: nrhs vectors of `elem`-byte entries; out: nrhs vectors (out_per_rhs) or one array of
-// N entries of out_elem bytes.
+// N entries of out_elem bytes; phi: N entries of phi_elem bytes.  The output may overlap
+// neither input (other workgroups still read them while it is written).
 hub_status check_vec_args(const hub_ctx* c, const void* phi, const void* in, const void* out, int nrhs,
-                          size_t elem, size_t out_elem, bool out_per_rhs) {
+                          size_t elem, size_t out_elem, bool out_per_rhs, size_t phi_elem) {
     if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
     if (!phi || !in || !out) return fail(HUB_ERR_ARG, "NULL array argument");
     if (nrhs < 1 || nrhs > c->nrhs_max)
@@ -235,12 +239,13 @@ hub_status check_vec_args(const hub_ctx* c, const void* phi, const void* in, con
     const size_t in_bytes = (size_t)nrhs * c->N * elem;
     const size_t out_bytes = (size_t)(out_per_rhs ? nrhs : 1) * c->N * out_elem;
     if (overlaps(in, in_bytes, out, out_bytes)) return fail(HUB_ERR_ARG, "input and output overlap");
+    if (overlaps(phi, (size_t)c->N * phi_elem, out, out_bytes)) return fail(HUB_ERR_ARG, "phi and output overlap");
     return HUB_OK;
 }
 
 template <typename R>
 hub_status apply_M_impl(hub_ctx* c, const R* phi, const void* in, void* out, int nrhs, void* stream) {
-    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
+    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true, sizeof(R));
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
     if (c->form == HUB_FORM_LINEAR)
@@ -252,7 +257,7 @@ hub_status apply_M_impl(hub_ctx* c, const R* phi, const void* in, void* out, int
 
 template <typename R>
 hub_status apply_Mdag_impl(hub_ctx* c, const R* phi, const void* in, void* out, int nrhs, void* stream) {
-    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true);
+    hub_status s = check_vec_args(c, phi, in, out, nrhs, sizeof(cx<R>), sizeof(cx<R>), true, sizeof(R));
     if (s != HUB_OK) return s;
     const cx<R>* v = static_cast<const cx<R>*>(in);
     if (c->form == HUB_FORM_LINEAR)
@@ -262,21 +267,32 @@ hub_status apply_Mdag_impl(hub_ctx* c, const R* phi, const void* in, void* out, 
                      CtlPlain{}, static_cast<hipStream_t>(stream));
 }
 
+// Solver workspace, allocated on the first solve.  After a failed allocation the
+// buffers already obtained stay with the context (hub_destroy frees them) and a later
+// call allocates only the missing ones.
 hub_status ensure_cg_workspace(hub_ctx* c) {
     if (c->cg_ready) return HUB_OK;
     const size_t vbytes = (size_t)c->nrhs_max * c->N * sizeof(cx<double>);
-    HIP_OR_FAIL(hipMalloc(&c->cg_rhi, vbytes));
-    HIP_OR_FAIL(hipMalloc(&c->cg_tmp, vbytes));
-    HIP_OR_FAIL(hipMalloc(&c->cg_x, vbytes));
-    HIP_OR_FAIL(hipMalloc(&c->cg_r, vbytes));
-    HIP_OR_FAIL(hipMalloc(&c->cg_p, vbytes));
-    HIP_OR_FAIL(hipMalloc(&c->cg_t, vbytes));
-    HIP_OR_FAIL(hipMalloc(&c->ph64, (size_t)c->N * sizeof(cx<double>)));
-    HIP_OR_FAIL(hipMalloc(&c->ph32, (size_t)c->N * sizeof(cx<float>)));
-    HIP_OR_FAIL(hipMalloc(&c->scal, (size_t)c->nrhs_max * sizeof(CgScalars)));
-    HIP_OR_FAIL(hipMalloc(&c->cg_pr, (size_t)3 * c->nrhs_max * c->max_partials * sizeof(double)));
-    HIP_OR_FAIL(hipMalloc(&c->cg_pt, (size_t)c->nrhs_max * c->max_partials * sizeof(double)));
-    HIP_OR_FAIL(hipHostMalloc(&c->scal_host, (size_t)c->nrhs_max * sizeof(CgScalars), hipHostMallocDefault));
+    const size_t pbytes = (size_t)c->nrhs_max * c->max_partials * sizeof(double);
+    struct Need {
+        void** p;
+        size_t bytes;
+    } need[] = {{&c->cg_rhi, vbytes},
+                {&c->cg_tmp, vbytes},
+                {&c->cg_x, vbytes},
+                {&c->cg_r, vbytes},
+                {&c->cg_p, vbytes},
+                {&c->cg_t, vbytes},
+                {&c->ph64, (size_t)c->N * sizeof(cx<double>)},
+                {&c->ph32, (size_t)c->N * sizeof(cx<float>)},
+                {reinterpret_cast<void**>(&c->scal), (size_t)c->nrhs_max * sizeof(CgScalars)},
+                {reinterpret_cast<void**>(&c->cg_pr), 3 * pbytes},
+                {reinterpret_cast<void**>(&c->cg_pt), pbytes}};
+    for (const Need& n : need)
+        if (!*n.p) HIP_OR_FAIL(hipMalloc(n.p, n.bytes));
+    if (!c->scal_host)
+        HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void**>(&c->scal_host), (size_t)c->nrhs_max * sizeof(CgScalars),
+                                  hipHostMallocDefault));
     c->cg_ready = true;
     return HUB_OK;
 }
@@ -555,7 +571,7 @@ hub_status hub_apply_Mdag_c64(hub_ctx* c, const float* phi, const void* in, void
 
 hub_status hub_cg_solve(hub_ctx* c, const double* phi, const void* chi, void* x, int32_t nrhs,
                         const hub_cg_opts* opts, hub_cg_info* info, void* stream) {
-    hub_status s = check_vec_args(c, phi, chi, x, nrhs, sizeof(cx<double>), sizeof(cx<double>), true);
+    hub_status s = check_vec_args(c, phi, chi, x, nrhs, sizeof(cx<double>), sizeof(cx<double>), true, sizeof(double));
     if (s != HUB_OK) return s;
     if (!opts) return fail(HUB_ERR_ARG, "opts is NULL");
     if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) return fail(HUB_ERR_ARG, "tol must be > 0");
@@ -574,10 +590,8 @@ hub_status hub_cg_solve(hub_ctx* c, const double* phi, const void* chi, void* x,
 }
 
 hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, int32_t nrhs, void* stream) {
-    hub_status s = check_vec_args(c, phi, x, g, nrhs, sizeof(cx<double>), sizeof(double), false);
+    hub_status s = check_vec_args(c, phi, x, g, nrhs, sizeof(cx<double>), sizeof(double), false, sizeof(double));
     if (s != HUB_OK) return s;
-    if (overlaps(g, (size_t)c->N * sizeof(double), phi, (size_t)c->N * sizeof(double)))
-        return fail(HUB_ERR_ARG, "dSdphi overlaps phi");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const cx<double>* xv = static_cast<const cx<double>*>(x);
     if (c->form == HUB_FORM_LINEAR) {

@@ -173,6 +173,12 @@ def test_cg_error_paths():
     with pytest.raises(HubError) as e:
         hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-10, stall_updates=-1)
     assert e.value.status == HUB_ERR_ARG
+    # outputs aliasing phi are refused before anything is launched
+    import ctypes
+    P, C = to_dev(phi), to_dev(chi)
+    pp, cp = ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(C.data_ptr())
+    assert hub.lib.hub_apply_M(hub._h, pp, cp, pp, 1, None) == HUB_ERR_ARG
+    assert hub.lib.hub_force(hub._h, pp, cp, pp, 1, None) == HUB_ERR_ARG
 
 
 def _free_cond(w):
