@@ -301,23 +301,34 @@ hub_status ensure_cg_workspace(hub_ctx* c) {
 template <typename Rlo>
 hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<double>* xhi, int nrhs,
                    const hub_cg_opts& o, hub_cg_info* info, hipStream_t st) {
-    // e^{i phi} once per solve, in FP64 and in the iteration precision
+    const bool lin = c->form == HUB_FORM_LINEAR;
+    // Phases: e^{i phi} tabulated once per solve in FP64, and in FP32 for FP32 iterations of
+    // the exponential form (transform-bound kernels).  FP32 iterations of the linear form
+    // (bandwidth-bound stencils) read an FP32 copy of the angles instead, half the bytes of
+    // a table, and evaluate the phase per use on the hardware sin/cos units.
     cx<double>* ph64 = static_cast<cx<double>*>(c->ph64);
+    const cx<Rlo>* ph_lo = reinterpret_cast<const cx<Rlo>*>(ph64);
+    const Rlo* phi_lo = reinterpret_cast<const Rlo*>(phi);
     hipLaunchKernelGGL(k_phase_table<double>, dim3(1024), dim3(kThreads), 0, st, phi, ph64, c->N);
     hub_status s0 = launch_check("k_phase_table<double>");
     if (s0 != HUB_OK) return s0;
-    const cx<Rlo>* ph_lo;
     if constexpr (sizeof(Rlo) == sizeof(float)) {
-        hipLaunchKernelGGL(k_phase_table<float>, dim3(1024), dim3(kThreads), 0, st, phi,
-                           static_cast<cx<float>*>(c->ph32), c->N);
-        s0 = launch_check("k_phase_table<float>");
+        if (!lin) {
+            hipLaunchKernelGGL(k_phase_table<float>, dim3(1024), dim3(kThreads), 0, st, phi,
+                               static_cast<cx<float>*>(c->ph32), c->N);
+            s0 = launch_check("k_phase_table<float>");
+            ph_lo = reinterpret_cast<const cx<Rlo>*>(c->ph32);
+        } else {
+            float* phi32 = static_cast<float*>(c->ph32);       // N floats in the table's space
+            hipLaunchKernelGGL(k_to_float, dim3(1024), dim3(kThreads), 0, st, phi, phi32, c->N);
+            s0 = launch_check("k_to_float");
+            phi_lo = reinterpret_cast<const Rlo*>(phi32);
+        }
         if (s0 != HUB_OK) return s0;
-        ph_lo = reinterpret_cast<const cx<Rlo>*>(c->ph32);
-    } else {
-        ph_lo = reinterpret_cast<const cx<Rlo>*>(ph64);
     }
     const PhTable<Rlo> tab_lo{ph_lo};
     const PhTable<double> tab64{ph64};
+    const PhAngle<Rlo> ang_lo{phi_lo};
     cx<double>* rhi = static_cast<cx<double>*>(c->cg_rhi);
     cx<double>* tmp = static_cast<cx<double>*>(c->cg_tmp);
     cx<Rlo>* xlo = static_cast<cx<Rlo>*>(c->cg_x);
@@ -327,7 +338,6 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     CgScalars* sc = c->scal;
     const int zero_start = o.use_x0 ? 0 : 1;
     const int blocks = nrhs * c->Nt;
-    const bool lin = c->form == HUB_FORM_LINEAR;
 
     // ||r||^2 partials of iterations i, i-1, i+1 rotate through three buffers (index i mod 3)
     const int slots = op_slots<Rlo>(c, nrhs);   // the iteration kernels' reduction slots
@@ -421,9 +431,15 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
             const CtlSearch k1{pr(i), pr(i + 2), pt, sc, slots};
             const CtlUpdate k2{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
             if (lin) {
-                s = run_lin<Rlo, true>(c, nrhs, tab_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
-                if (s != HUB_OK) return s;
-                s = run_lin<Rlo, false>(c, nrhs, tab_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
+                if constexpr (sizeof(Rlo) == sizeof(float)) {
+                    s = run_lin<Rlo, true>(c, nrhs, ang_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
+                    if (s != HUB_OK) return s;
+                    s = run_lin<Rlo, false>(c, nrhs, ang_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
+                } else {
+                    s = run_lin<Rlo, true>(c, nrhs, tab_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
+                    if (s != HUB_OK) return s;
+                    s = run_lin<Rlo, false>(c, nrhs, tab_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
+                }
                 if (s != HUB_OK) return s;
                 continue;
             }

@@ -215,3 +215,53 @@ def test_sublattice_and_split_kernels_agree(dag):
     fa = a.apply_Mdag_c64 if dag else a.apply_M_c64
     fb = b.apply_Mdag_c64 if dag else b.apply_M_c64
     assert_close_elementwise(to_np(fa(P32, V32)), to_np(fb(P32, V32)), 4e-6, "sub vs split")
+
+
+@pytest.mark.parametrize("form", ["exp", "linear"])
+def test_graph_replays_match_eager(form):
+    """The operators captured in a HIP graph (the way the benchmark times them): every
+    replay, with eager work and synchronisations between replays, equals the eager result
+    bit for bit."""
+    from paper_2210_06874_amd import Hubbard
+    w = PREC
+    print(f"[case] graph replays {form}", flush=True)
+    phi, v = draw_inputs(w, seed=19)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, form=form)
+    P32, V32 = to_dev(phi.astype(np.float32)), to_dev(v.astype(np.complex64))
+    P, V = to_dev(phi), to_dev(v)
+    eager32 = hub.apply_M_c64(P32, V32).clone()
+    eager64 = hub.apply_Mdag(P, V).clone()
+    out32, out64 = torch.empty_like(V32), torch.empty_like(V)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(3):
+                hub.apply_M_c64(P32, V32, out=out32)
+                hub.apply_Mdag(P, V, out=out64)
+    for rep in range(4):
+        out32.zero_()
+        out64.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out32, eager32), rep
+        assert torch.equal(out64, eager64), rep
+        hub.apply_M(P, V)                     # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_operators_on_a_side_stream():
+    """Calls enqueue on the caller's current stream (here a side stream, default priority)."""
+    w = SMALL
+    phi, v = draw_inputs(w, seed=20)
+    hub = _hub(w)
+    P, V = to_dev(phi), to_dev(v)
+    ref = hub.apply_M(P, V).clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        got = hub.apply_M(P, V)
+        res = hub.cg_solve(P, V, tol=1e-8, prec="mixed")
+    s.synchronize()
+    assert torch.equal(got, ref)
+    assert res.converged
