@@ -265,3 +265,53 @@ def test_operators_on_a_side_stream():
     s.synchronize()
     assert torch.equal(got, ref)
     assert res.converged
+
+
+MAXL = Lattice("L1024_Nt2", 1024, 2, 0.5, 3.0)      # the largest torus the ABI accepts
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_maximum_lattice(prec):
+    """L = 1024 (2 M sites per slice, the split path with runtime radix-4 plans), every
+    entry against the oracle's Krylov-exp route."""
+    w = MAXL
+    print(f"[case] apply {prec} {w.name}", flush=True)
+    phi, v = draw_inputs(w, seed=21)
+    hub = _hub(w)
+    assert hub.path == "split"
+    op = oracle_op(w, mode="expm")
+    if prec == "fp64":
+        got = to_np(hub.apply_M(to_dev(phi), to_dev(v)))
+        ref = op.apply_M(phi, v)
+        tol = RTOL64
+    else:
+        p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
+        got = to_np(hub.apply_M_c64(to_dev(p32), to_dev(v32)))
+        ref = op.apply_M(p32.astype(np.float64), v32.astype(np.complex128))
+        tol = RTOL32
+    assert_close_elementwise(got, ref, tol, "M")
+
+
+@pytest.mark.parametrize("form", ["exp", "linear"])
+def test_kappa_zero_is_a_pure_time_hop(form):
+    """kappa = 0 (degenerate: no spatial hopping, E = 1): every site is an independent
+    antiperiodic time chain, written out here directly from the operator's definition."""
+    from paper_2210_06874_amd import Hubbard
+    w = SMALL
+    phi, v = draw_inputs(w, seed=22)
+    hub = Hubbard(w.L, w.Nt, w.beta, 0.0, form=form)
+    got = to_np(hub.apply_M(to_dev(phi), to_dev(v)))[0]
+    v0 = v[0]
+    B = np.ones(w.Nt)
+    B[0] = -1.0
+    e = np.exp(1j * phi)
+    prev = B[:, None] * np.roll(v0, 1, axis=0)              # B_t v_{t-1}
+    if form == "exp":
+        ref = v0 - B[:, None] * np.roll(e * v0, 1, axis=0)  # v_t - B_t e^{i phi_{t-1}} v_{t-1}
+    else:
+        nxt = np.roll(B, -1)[:, None] * np.roll(v0, -1, axis=0)   # B_{t+1} v_{t+1}
+        LL = w.L * w.L
+        ref = np.empty_like(v0)
+        ref[:, :LL] = nxt[:, :LL] - e[:, :LL] * v0[:, :LL]
+        ref[:, LL:] = v0[:, LL:] - np.conj(e[:, LL:]) * prev[:, LL:]
+    assert_close_elementwise(got, ref, RTOL64, "kappa=0")

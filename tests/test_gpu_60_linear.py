@@ -260,3 +260,14 @@ def _free_cond_linear(w):
     det = np.abs(a * d - g ** 2) ** 2
     disc = np.sqrt(np.maximum(tr ** 2 - 4 * det, 0))
     return ((tr + disc) / 2).max() / ((tr - disc) / 2).min()
+
+
+def test_apply_maximum_lattice():
+    """L = 1024, N_t = 2 (the largest torus the ABI accepts), every entry of M and M^dag."""
+    w = Lattice("L1024_Nt2", 1024, 2, 0.5, 3.0)
+    print(f"[case] linear apply {w.name}", flush=True)
+    phi, v = draw_inputs(w, seed=75)
+    hub = _hub(w)
+    op = _op(w)
+    assert_close_elementwise(to_np(hub.apply_M(to_dev(phi), to_dev(v))), op.apply_M(phi, v), RTOL64, "M")
+    assert_close_elementwise(to_np(hub.apply_Mdag(to_dev(phi), to_dev(v))), op.apply_Mdag(phi, v), RTOL64, "Mdag")
