@@ -142,3 +142,16 @@ def test_momentum_hopping_table_is_the_2x2_exponential(tmp_path, L, dk, dmu):
 def test_unsupported_lengths_have_no_plan(tmp_path):
     assert _tables(tmp_path, 19, 0.1) is None
     assert _tables(tmp_path, 23 * 2, 0.1) is None
+
+
+def test_plain_c_client_compiles_and_links(tmp_path):
+    """The C ABI is usable from C alone: the client in tests/host/abi_driver.c builds with
+    gcc against include/hub.h and the library, and starts (usage message without args)."""
+    exe = tmp_path / "abi_driver"
+    subprocess.run(["gcc", "-std=c99", "-O2", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "host", "abi_driver.c"),
+                    "-L", os.path.join(ROOT, "paper_2210_06874_amd"), "-lhubhip", "-L/opt/rocm/lib", "-lamdhip64",
+                    "-Wl,-rpath," + os.path.join(ROOT, "paper_2210_06874_amd"), "-Wl,-rpath,/opt/rocm/lib",
+                    "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 1 and "usage" in r.stderr
