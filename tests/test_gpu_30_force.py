@@ -111,3 +111,31 @@ def test_cg_and_force_with_chemical_potential():
     assert_close_elementwise(g, O.force(op, phi, x), 1e-12, "force")
     gd = O.force_dense(op, phi, O.dense_solve(op, phi, chi))
     assert np.linalg.norm(g - gd) <= 1e-7 * np.linalg.norm(gd)
+
+
+def test_precision_workload_end_to_end():
+    """L = 51, N_t = 128, weak field, heat-bath chi = M rho: the mixed-precision solve meets
+    1e-10 on the residual the oracle recomputes, and its force is within 1e-8 of the
+    oracle's force on an FP64 solution to 1e-12 (itself checked through M^dag x = rho)."""
+    from workloads import draw_weak_field
+    w = PREC
+    print(f"[case] end to end {w.name}", flush=True)
+    phi, _ = draw_weak_field(w)
+    rho = draw_complex(w, seed=7)
+    op = oracle_op(w, mode="expm")
+    chi = op.apply_M(phi, rho)
+    hub = _hub(w)
+    P, C = to_dev(phi), to_dev(chi)
+    mixed = hub.cg_solve(P, C, tol=1e-10, prec="mixed")
+    tight = hub.cg_solve(P, C, tol=1e-12, prec="fp64", max_iter=40000)
+    assert mixed.converged and tight.converged
+    xm, xt = to_np(mixed.x), to_np(tight.x)
+    rr = np.linalg.norm(chi - op.apply_A(phi, xm)) / np.linalg.norm(chi)
+    assert rr <= 1.01e-10, rr
+    hb = np.linalg.norm(op.apply_Mdag(phi, xt) - rho) / np.linalg.norm(rho)
+    assert hb <= 1e-9, hb
+    g_ref = O.force(op, phi, xt)
+    g = to_np(hub.force(P, mixed.x))
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"    residual {rr:.2e}, heat bath {hb:.2e}, force error {err:.2e}", flush=True)
+    assert err <= 1e-8, err
