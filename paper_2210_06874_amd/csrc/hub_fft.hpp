@@ -22,8 +22,6 @@ struct alignas(2 * sizeof(R)) cx {
 };
 
 template <typename R>
-__device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
-template <typename R>
 __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename R>
 __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }

@@ -61,12 +61,6 @@ __device__ __forceinline__ double block_allsum(double v, double* lds) {
     return bcast;
 }
 
-// Sum of `n` partials in slot order, returned to every thread.
-__device__ __forceinline__ double sum_partials(const double* p, int n, double* lds) {
-    double v = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) v += p[j];
-    return block_allsum(v, lds);
-}
 
 // K sums of `n` partials each, in slot order, returned to every thread: all loads are
 // issued before the first is used and the K block reductions share one pair of barriers.
