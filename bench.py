@@ -134,6 +134,28 @@ def cpu_baseline(w, phi, chi, budget_s: float = 15.0):
                       f"{blas[0]['internal_api'] if blas else 'none'} unused"}
 
 
+def nrhs_scan(w, dev) -> dict:
+    """FP32 application of 1, 2, 4, 8 right-hand sides in one launch (context for the roofline:
+    at L = 51 one right-hand side gives 128 slices for 256 compute units)."""
+    import torch
+    from paper_2210_06874_amd import Hubbard
+    from workloads import draw_inputs
+    out = {}
+    for form in ("exp", "linear"):
+        hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, nrhs_max=8, device=dev, form=form)
+        rows = {}
+        for n in (1, 2, 4, 8):
+            phi, chi = draw_inputs(w, nrhs=n)
+            p32 = torch.from_numpy(phi).to(dev).float()
+            c32 = torch.from_numpy(chi).to(dev).to(torch.complex64)
+            o = torch.empty_like(c32)
+            t = time_graph(lambda: hub.apply_M_c64(p32, c32, out=o), per_graph=20, replays=5)
+            rows[str(n)] = {"us_per_launch": t * 1e6, "us_per_rhs": t * 1e6 / n,
+                            "hbm_frac": 20.0 * w.N * n / t / 1e9 / HBM_PEAK_GBS}
+        out[form] = rows
+    return out
+
+
 def linear_leg(w, dev, P, C, P32, V32, out32, steps: int, warmup: int) -> dict:
     """The force step and the FP32 apply roofline with the linear form of the operator."""
     import torch
@@ -278,6 +300,7 @@ def main() -> int:
               "avg_launch_us": t_k64 * 1e6, "alg_bytes_per_launch": alg64}
 
     lin = linear_leg(w, dev, P, C, P32, V32, out32, args.steps, args.warmup)
+    batching = nrhs_scan(w, dev)
 
     # the timed step is almost all CG iterations: two operator kernels that move 96 B per
     # site-slice in FP32 (M^dag step: read r, p, e^{i phi}, write t; update step: read t, p,
@@ -332,6 +355,7 @@ def main() -> int:
         "roofline": roof,
         "roofline_apply_M_fp64": roof64,
         "linear_form": lin,
+        "batching": batching,
         "literal_field_probe": probe,
         "cpu_baseline": None,
     }
