@@ -139,3 +139,49 @@ def test_precision_workload_end_to_end():
     err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
     print(f"    residual {rr:.2e}, heat bath {hb:.2e}, force error {err:.2e}", flush=True)
     assert err <= 1e-8, err
+
+
+def test_autograd_against_finite_differences_differentiation_workload():
+    """L = 24, N_t = 64, beta = 8 (weak field: the prior draws do not converge at beta = 8):
+    the autograd backward (the adjoint force kernel) against central finite differences at
+    eps = 1e-6 on 64 random entries, each difference free of cancellation.  phi_{t,z} enters
+    M only through column (t, z) of block (t+1, t): M = M' + e^{i phi} u e^T with
+    u = -B_{t+1} E[:, z] on slice t+1.  Hence, with x+- = (M+- M+-^dag)^{-1} chi and
+    Delta = e^{i phi-} - e^{i phi+},
+        S+ - S- = x+^dag (A- - A+) x- = Delta conj(u^dag x+) x-_{t,z} + conj(Delta) conj(x+_{t,z}) u^dag x-,
+    and u^dag x = -e^{i phi_{t,z}} (x - M^dag x)_{t,z} (from the (t, z) entry of M^dag x).
+    Every term is O(|x|^2 eps): no large quantities are subtracted.  x+- are solved on the
+    device to 1e-13 and M^dag x+- applied there.  Bar: 1e-8 on the norm over the 64 entries."""
+    from paper_2210_06874_amd import PseudofermionAction
+    from workloads import DIFF, draw_weak_field, pick_entries
+    w = DIFF
+    print(f"[case] finite differences {w.name}", flush=True)
+    phi, chi = draw_weak_field(w)
+    hub = _hub(w)
+    P = to_dev(phi).requires_grad_(True)
+    C = to_dev(chi)
+    S = PseudofermionAction.apply(P, C, hub, 1e-13)
+    S.backward()
+    g = to_np(P.grad).ravel()
+    eps = 1e-6
+    idx = pick_entries(w, 64)
+    fd = np.empty(len(idx))
+    for n, j in enumerate(idx):
+        t, z = divmod(int(j), w.V)
+        sides = {}
+        for sgn in (+1, -1):
+            ph = phi.copy()
+            ph[t, z] += sgn * eps
+            Pd = to_dev(ph)
+            x = hub.cg_solve(Pd, C, tol=1e-13, max_iter=40000).x
+            y = hub.apply_Mdag(Pd, x)
+            xe = complex(to_np(x[0, t, z]))
+            d = xe - complex(to_np(y[0, t, z]))
+            sides[sgn] = (ph[t, z], xe, -np.exp(1j * ph[t, z]) * d)       # (phi, x_{t,z}, u^dag x)
+        (pp, xp, up), (pm, xm, um) = sides[+1], sides[-1]
+        delta = np.exp(1j * pm) - np.exp(1j * pp)
+        dS = delta * np.conj(up) * xm + np.conj(delta) * np.conj(xp) * um
+        fd[n] = dS.real / (2 * eps)
+    err = np.linalg.norm(fd - g[idx]) / np.linalg.norm(g[idx])
+    print(f"    finite-difference error {err:.2e} over {len(idx)} entries", flush=True)
+    assert err <= 1e-8, err
