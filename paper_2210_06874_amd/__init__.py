@@ -14,7 +14,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import HubError, HUB_ERR_NOCONV, HUB_OK
+from ._lib import HubError, HUB_OK
 
 __all__ = ["Hubbard", "CgResult", "HubError", "PseudofermionAction"]
 
@@ -105,10 +105,19 @@ class Hubbard:
         return ctypes.c_void_p(t.data_ptr())
 
     # ------------------------------------------------------------------ operators
+    def _out(self, out, like: torch.Tensor, name="out") -> torch.Tensor:
+        """A caller-supplied output must match what the kernels write exactly: the library
+        sees only its pointer, so a short or strided buffer would be overrun."""
+        if (not isinstance(out, torch.Tensor) or out.device != like.device or out.dtype != like.dtype
+                or tuple(out.shape) != tuple(like.shape) or not out.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {like.dtype} tensor of shape "
+                             f"{tuple(like.shape)} on {like.device}")
+        return out
+
     def _apply(self, fn, phi, v, cdtype, rdtype, out=None):
         phi = self._phi(phi, rdtype)
         v3, nrhs = self._vec(v, cdtype)
-        o = torch.empty_like(v3) if out is None else out
+        o = torch.empty_like(v3) if out is None else self._out(out, v).view(v3.shape)
         with torch.cuda.device(self.device):
             _lib.check(fn(self._h, self._p(phi), self._p(v3), self._p(o), nrhs, _stream_ptr(self.device)))
         return o if v.dim() == 3 else o[0]
@@ -152,9 +161,7 @@ class Hubbard:
         with torch.cuda.device(self.device):
             st = self.lib.hub_cg_solve(self._h, self._p(phi), self._p(chi3), self._p(x), nrhs,
                                        ctypes.byref(opts), info, _stream_ptr(self.device))
-        if st not in (HUB_OK, HUB_ERR_NOCONV) and raise_on_error:
-            _lib.check(st)
-        if st == HUB_ERR_NOCONV and raise_on_error:
+        if raise_on_error:
             _lib.check(st)
         res = CgResult(x if chi.dim() == 3 else x[0], st,
                        [i.iters for i in info], [i.reliable_updates for i in info],
@@ -165,7 +172,8 @@ class Hubbard:
         """dS/dphi (float64 [Nt, V]) of S = chi^dag (M M^dag)^{-1} chi from the solutions x."""
         phi = self._phi(phi)
         x3, nrhs = self._vec(x, name="x")
-        g = torch.empty((self.Nt, self.V), dtype=torch.float64, device=self.device) if out is None else out
+        g = torch.empty((self.Nt, self.V), dtype=torch.float64, device=self.device) if out is None \
+            else self._out(out, phi)
         with torch.cuda.device(self.device):
             _lib.check(self.lib.hub_force(self._h, self._p(phi), self._p(x3), self._p(g), nrhs,
                                           _stream_ptr(self.device)))

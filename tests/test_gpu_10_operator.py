@@ -315,3 +315,33 @@ def test_kappa_zero_is_a_pure_time_hop(form):
         ref[:, :LL] = nxt[:, :LL] - e[:, :LL] * v0[:, :LL]
         ref[:, LL:] = v0[:, LL:] - np.conj(e[:, LL:]) * prev[:, LL:]
     assert_close_elementwise(got, ref, RTOL64, "kappa=0")
+
+
+def test_output_buffers_are_checked():
+    """The binding refuses an out tensor the kernels would overrun or misread (short, strided,
+    wrong dtype or device) and writes a correct one in place, 2-D or 3-D."""
+    from paper_2210_06874_amd import Hubbard
+    w = TINY
+    phi, v = draw_inputs(w)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa)
+    P, V = to_dev(phi), to_dev(v[0])
+    ref = hub.apply_M(P, V)
+    bad = [torch.empty((w.Nt, w.V - 1), dtype=torch.complex128, device=dev()),
+           torch.empty((w.Nt, w.V), dtype=torch.complex64, device=dev()),
+           torch.empty((w.V, w.Nt), dtype=torch.complex128, device=dev()).t(),
+           torch.empty((w.Nt, w.V), dtype=torch.complex128)]
+    for o in bad:
+        with pytest.raises(ValueError):
+            hub.apply_M(P, V, out=o)
+    with pytest.raises(ValueError):
+        hub.force(P, V, out=torch.empty((w.Nt, w.V), dtype=torch.float32, device=dev()))
+    o2 = torch.empty_like(V)
+    r2 = hub.apply_M(P, V, out=o2)
+    assert r2.data_ptr() == o2.data_ptr() and torch.equal(o2, ref)
+    o3 = torch.empty((1, w.Nt, w.V), dtype=torch.complex128, device=dev())
+    with pytest.raises(ValueError):
+        hub.apply_M(P, V, out=o3)            # out must have the input's own shape
+    r3 = hub.apply_M(P, V[None], out=o3)
+    assert r3.data_ptr() == o3.data_ptr() and torch.equal(o3[0], ref)
+    g = torch.empty_like(P)
+    assert hub.force(P, V, out=g).data_ptr() == g.data_ptr()
