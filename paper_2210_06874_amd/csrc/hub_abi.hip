@@ -293,6 +293,7 @@ hub_status ensure_cg_workspace(hub_ctx* c) {
     if (!c->scal_host)
         HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void**>(&c->scal_host), (size_t)c->nrhs_max * sizeof(CgScalars),
                                   hipHostMallocDefault));
+    if (!c->cg_event) HIP_OR_FAIL(hipEventCreateWithFlags(&c->cg_event, hipEventDisableTiming));
     c->cg_ready = true;
     return HUB_OK;
 }
@@ -380,15 +381,55 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
         if (s != HUB_OK) return s;
     }
 
+    // Iterations i = from .. from + n - 1 (two kernels each).
+    auto queue_iters = [&](long long from, long long n) -> hub_status {
+        for (long long i = from; i < from + n; ++i) {
+            const CtlSearch k1{pr(i), pr(i + 2), pt, sc, slots};
+            const CtlUpdate k2{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
+            hub_status q;
+            if (lin) {
+                if constexpr (sizeof(Rlo) == sizeof(float)) {
+                    q = run_lin<Rlo, true>(c, nrhs, ang_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
+                    if (q != HUB_OK) return q;
+                    q = run_lin<Rlo, false>(c, nrhs, ang_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
+                } else {
+                    q = run_lin<Rlo, true>(c, nrhs, tab_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
+                    if (q != HUB_OK) return q;
+                    q = run_lin<Rlo, false>(c, nrhs, tab_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
+                }
+            } else {
+                q = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p},
+                                EpiSearchMdag<Rlo, PhTable<Rlo>>{rlo, p, tv, tab_lo}, k1, st);
+                if (q != HUB_OK) return q;
+                q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhTable<Rlo>>{tv, tab_lo},
+                                EpiUpdate<Rlo>{tv, p, xlo, rlo}, k2, st);
+            }
+            if (q != HUB_OK) return q;
+        }
+        return HUB_OK;
+    };
+
     hub_status result = HUB_OK;
-    long long it = 0;
+    long long it = 0;                  // iterations queued so far
     const int every = o.reliable_every;
+    // The host reads the scalars of each reliable update while the device already runs the
+    // first iterations of the next block, so the device does not idle during the read.  Those
+    // iterations are harmless when the host then stops: every kernel of a finished right-hand
+    // side is idle, and otherwise they touch only the iteration vectors, never x or the
+    // scalars' host copy, which describe the state at the reliable update.
+    const long long lookahead = std::min<long long>(4, every);
     // stagnation watch: per rhs, the best true ||r||^2 seen and the consecutive stalled updates
     std::vector<double> best(nrhs, HUGE_VAL);
     std::vector<int> seen(nrhs, 0), stalled(nrhs, 0);
     for (;;) {
         HIP_OR_FAIL(hipMemcpyAsync(c->scal_host, sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, st));
-        HIP_OR_FAIL(hipStreamSynchronize(st));
+        HIP_OR_FAIL(hipEventRecord(c->cg_event, st));
+        const long long at = it;       // iterations behind the scalars being read
+        const long long head = std::min<long long>(lookahead, o.max_iter - it);
+        s = queue_iters(it, head);
+        if (s != HUB_OK) return s;
+        it += head;
+        HIP_OR_FAIL(hipEventSynchronize(c->cg_event));
         bool all_done = true, bad = false, all_stalled = true;
         for (int r = 0; r < nrhs; ++r) {
             const CgScalars& h = c->scal_host[r];
@@ -421,39 +462,19 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
                           o.stall_updates, o.tol);
             break;
         }
-        if (it >= o.max_iter) {
+        if (at >= o.max_iter) {
             result = fail(HUB_ERR_NOCONV, "CG did not reach tol=%g within max_iter=%d", o.tol, o.max_iter);
             break;
         }
-        const long long n = std::min<long long>(every, o.max_iter - it);
-        for (long long k = 0; k < n; ++k) {
-            const long long i = it + k;
-            const CtlSearch k1{pr(i), pr(i + 2), pt, sc, slots};
-            const CtlUpdate k2{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
-            if (lin) {
-                if constexpr (sizeof(Rlo) == sizeof(float)) {
-                    s = run_lin<Rlo, true>(c, nrhs, ang_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
-                    if (s != HUB_OK) return s;
-                    s = run_lin<Rlo, false>(c, nrhs, ang_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
-                } else {
-                    s = run_lin<Rlo, true>(c, nrhs, tab_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
-                    if (s != HUB_OK) return s;
-                    s = run_lin<Rlo, false>(c, nrhs, tab_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
-                }
-                if (s != HUB_OK) return s;
-                continue;
-            }
-            s = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p}, EpiSearchMdag<Rlo, PhTable<Rlo>>{rlo, p, tv, tab_lo},
-                            k1, st);
-            if (s != HUB_OK) return s;
-            s = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhTable<Rlo>>{tv, tab_lo}, EpiUpdate<Rlo>{tv, p, xlo, rlo},
-                            k2, st);
-            if (s != HUB_OK) return s;
-        }
+        const long long n = std::min<long long>(every - head, o.max_iter - it);
+        s = queue_iters(it, n);
+        if (s != HUB_OK) return s;
         it += n;
         s = reliable_update(it);
         if (s != HUB_OK) return s;
     }
+    // the iterations queued ahead end before the call returns
+    HIP_OR_FAIL(hipStreamSynchronize(st));
     if (info) {
         for (int r = 0; r < nrhs; ++r) {
             const CgScalars& h = c->scal_host[r];
@@ -569,6 +590,7 @@ void hub_destroy(hub_ctx* c) {
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->scal_host) (void)hipHostFree(c->scal_host);
+    if (c->cg_event) (void)hipEventDestroy(c->cg_event);
     delete c;
 }
 

@@ -75,5 +75,6 @@ struct hub_ctx {
     double* cg_pr = nullptr;             // ||r||^2 partials, [3][nrhs_max][max_partials]
     double* cg_pt = nullptr;             // ||M^dag p||^2 partials, [nrhs_max][max_partials]
     hub::CgScalars* scal_host = nullptr; // pinned host mirror
+    hipEvent_t cg_event = nullptr;       // marks the copy of the scalars into scal_host
     double* force_tmp = nullptr;         // [nrhs_max][N] doubles, per-rhs force before summation (hub_create)
 };
