@@ -65,7 +65,7 @@ typedef enum {
     HUB_ERR_ARG = 1,        /* invalid argument (null pointer, size, aliasing, option) */
     HUB_ERR_DEVICE = 2,     /* a HIP runtime call failed                               */
     HUB_ERR_NOMEM = 3,      /* device allocation failed                                */
-    HUB_ERR_NOCONV = 4,     /* CG reached max_iter before the true residual met tol     */
+    HUB_ERR_NOCONV = 4,     /* CG stopped (max_iter, stagnation) before meeting tol     */
     HUB_ERR_NONFINITE = 5   /* NaN or Inf appeared in a CG scalar                      */
 } hub_status;
 
