@@ -93,10 +93,14 @@ void allow_lds(K kern, size_t bytes) {
 // (blocks per right-hand side) it has.
 enum class OpKind { Generic, Whole51, Half51, Split, Linear, Sub102 };
 
+// Workgroup size of the sublattice-at-a-time kernel.  Its 84 KB tile allows one workgroup
+// per compute unit, so the waves per CU are the workgroup's own: twelve (three per SIMD)
+// hide more latency than eight, at the price of a few register spills outside the
+// butterfly loops; sixteen spill more.
 #ifndef HUB_THREADS_SUB
-#define HUB_THREADS_SUB 512
+#define HUB_THREADS_SUB 768
 #endif
-constexpr int kThreadsSub = HUB_THREADS_SUB;   // workgroup size of the sublattice-at-a-time kernel
+constexpr int kThreadsSub = HUB_THREADS_SUB;
 
 #ifndef HUB_LIN_BATCH
 #define HUB_LIN_BATCH 3
