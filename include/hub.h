@@ -84,7 +84,9 @@ typedef struct {
     int32_t Nt;         /* time slices, Nt >= 1                                                 */
     double beta;        /* inverse temperature, delta = beta/Nt                                 */
     double kappa;       /* hopping amplitude                                                    */
-    int32_t nrhs_max;   /* largest nrhs any call on this context will pass, >= 1                */
+    int32_t nrhs_max;   /* largest nrhs any call on this context will pass, >= 1; nrhs_max * N
+                           < 2^40 and each launch grid (about 2 * nrhs_max * Nt blocks) within
+                           2^31 - 1, else HUB_ERR_ARG                                            */
     int32_t path;       /* hub_path                                                              */
     double mu;          /* chemical potential: every time hop carries e^{delta mu} (0 = half filling) */
     int32_t form;       /* hub_form; HUB_FORM_LINEAR ignores `path` and requires mu == 0       */

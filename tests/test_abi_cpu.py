@@ -55,7 +55,8 @@ def test_argument_errors_before_any_device_call():
     assert b"NULL" in lib.hub_last_error()
     for bad in [dict(L=0), dict(L=19), dict(L=2048), dict(Nt=0), dict(nrhs_max=0), dict(path=7),
                 dict(beta=float("nan")), dict(mu=float("inf")), dict(form=2), dict(form=-1),
-                dict(form=1, mu=0.5), dict(form=1, L=1025)]:
+                dict(form=1, mu=0.5), dict(form=1, L=1025),
+                dict(Nt=2**30, nrhs_max=4), dict(form=1, Nt=2**30, nrhs_max=4)]:   # launch grid
         prm = dict(L=3, Nt=8, beta=2.0, kappa=1.0, nrhs_max=1, path=0, mu=0.0, form=0)
         prm.update(bad)
         p = L.HubParams(prm["L"], prm["Nt"], prm["beta"], prm["kappa"], prm["nrhs_max"], prm["path"], prm["mu"],
