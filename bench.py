@@ -331,6 +331,9 @@ def main() -> int:
         "metric": METRIC,
         "value": applies / dt,
         "unit": "M-applications/s",
+        "value_definition": "applications of the fermion matrix M or M^dag per second (not millions): "
+                            "2 per CG iteration, 2 per reliable update and 1 for the force, over the "
+                            "timed wall time of the force steps",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
