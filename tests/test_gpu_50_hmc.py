@@ -77,3 +77,29 @@ def test_trajectory_reversible_on_device():
     md(P, Pi, chi, 6, 0.05)
     np.testing.assert_allclose(to_np(P), phi0, atol=1e-9)
     np.testing.assert_allclose(-to_np(Pi), pi, atol=1e-9)
+
+
+@pytest.mark.parametrize("form", ["exp", "linear"])
+def test_markov_chain_matches_oracle_chain(form):
+    """Sixty trajectories of a Markov chain on a 2 x 2 torus (N_t = 4, beta = 1, U = 2) from
+    phi = 0, at a step size that rejects about one in five: the device chain and the oracle
+    chain, driven by the same random numbers and each evolving its own field, take the same
+    accept/reject decisions with the same dH, and their fields stay together."""
+    from paper_2210_06874_amd import Hubbard, hmc
+    from workloads import Lattice
+    w = Lattice("L2_Nt4", 2, 4, 1.0, 2.0)
+    print(f"[case] hmc chain {form} {w.name}", flush=True)
+    cls = O.LinearHubbardOperator if form == "linear" else O.HubbardOperator
+    op = cls(w.L, w.Nt, w.beta, w.kappa)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, form=form)
+    phi_ref = np.zeros((w.Nt, w.V))
+    P = to_dev(phi_ref)
+    decisions = []
+    for k, (pi, rho, u) in enumerate(draw_hmc_randoms(w, 60, seed=1)):
+        _, _, dH_ref, acc_ref, phi_ref = OH.trajectory(op, w.U, phi_ref, pi, rho, u, n_md=5, eps=0.2)
+        tr = hmc.trajectory(hub, P, w.U, to_dev(pi), to_dev(rho), u, n_md=5, eps=0.2, tol=1e-12, prec="fp64")
+        assert tr.accepted == acc_ref, k
+        assert abs(tr.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref)), (k, tr.dH, dH_ref)
+        np.testing.assert_allclose(to_np(P), phi_ref, rtol=0, atol=1e-8, err_msg=f"trajectory {k}")
+        decisions.append(acc_ref)
+    assert 0 < decisions.count(False) < 30     # the chain both accepts and rejects
