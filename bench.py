@@ -203,9 +203,9 @@ def main() -> int:
                     help="only run 20 FP32 operator launches and a 64 MiB copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; the path shards over independent "
-              "right-hand sides or time slices (see the design notes), --gpus must be 1",
-              file=sys.stderr)
+        print("bench.py: the library runs on one GPU and this benchmark measures one GPU; "
+              "--gpus must be 1 (several GPUs would each take independent right-hand sides or a "
+              "block of time slices)", file=sys.stderr)
         return 2
 
     import numpy as np
