@@ -8,9 +8,10 @@ counted once; per CG iteration 2, per FP64 residual recomputation 2, the force 1
 over the timed steps.
 
 The input field is labelled: phi drawn from N(0, sqrt(delta U)) and scaled by
-delta ("weak field"), chi iid Gaussian.  With the unscaled prior draws the CG does
-not converge at beta = 8 (reported separately as per-iteration cost with
---literal-probe), see the design notes.
+delta ("weak field"), chi iid Gaussian.  With the unscaled prior draws (not
+thermalised by the weight det(M M^dag)) M M^dag is so ill-conditioned at beta = 8
+that the CG does not converge; their per-iteration cost is reported separately
+(--literal-probe).
 
 Also measured (not part of `value`):
   * the FP64 force step (s per force, FP64 vs mixed);
