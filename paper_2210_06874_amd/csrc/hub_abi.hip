@@ -47,12 +47,25 @@ hub_status launch_check(const char* what) {
     return HUB_OK;
 }
 
-SplitGeom split_geom(int L) {
+// Split-path tiles: about this many complex entries per row block and per column block
+// (both sublattices), rounded to an even division of L.
+#ifndef HUB_SPLIT_ROW_ELEMS
+#define HUB_SPLIT_ROW_ELEMS 2048
+#endif
+#ifndef HUB_SPLIT_COL_ELEMS
+#define HUB_SPLIT_COL_ELEMS 2048
+#endif
+#ifndef HUB_THREADS_SPLIT
+#define HUB_THREADS_SPLIT 256
+#endif
+constexpr int kThreadsSplit = HUB_THREADS_SPLIT;   // workgroup size of the compile-time split kernels
+
+constexpr SplitGeom split_geom(int L) {
     SplitGeom g{};
-    int rb0 = std::max(1, std::min(L, 2048 / L));
+    int rb0 = std::max(1, std::min(L, HUB_SPLIT_ROW_ELEMS / L));
     g.nrb = (L + rb0 - 1) / rb0;
     g.rb = (L + g.nrb - 1) / g.nrb;
-    int cb0 = std::max(1, std::min(L, 1024 / L));
+    int cb0 = std::max(1, std::min(L, HUB_SPLIT_COL_ELEMS / L));
     g.ncb = (L + cb0 - 1) / cb0;
     g.cb = (L + g.ncb - 1) / g.ncb;
     return g;
@@ -146,6 +159,31 @@ int op_slots(const hub_ctx* c, int nrhs) {
     }
 }
 
+// The split path with L and its tiles known at compile time.
+template <typename R, int L, int RB, int CB, class Src, class Epi, class Ctl>
+hub_status run_split_ct(hub_ctx* c, int nrhs, const OpTab<R>& T, const Src& src, const Epi& epi, const Ctl& ctl,
+                        hipStream_t st) {
+    cx<R>* W = reinterpret_cast<cx<R>*>(c->split_w);
+    const size_t lds_rows = (size_t)(RB * L + L) * sizeof(cx<R>);
+    const size_t lds_cols = (size_t)(2 * L * CB + L) * sizeof(cx<R>);
+    auto k1 = k_split_rows_fwd_ct<R, L, RB, kThreadsSplit, Src, Ctl>;
+    auto k2 = k_split_cols_ct<R, L, CB, kThreadsSplit, Ctl>;
+    auto k3 = k_split_rows_inv_ct<R, L, RB, kThreadsSplit, Epi, Ctl>;
+    allow_lds(k1, lds_rows);
+    allow_lds(k2, lds_cols);
+    allow_lds(k3, lds_rows);
+    const int nrow_blocks = nrhs * c->Nt * 2 * (L / RB);
+    hipLaunchKernelGGL(k1, dim3(nrow_blocks), dim3(kThreadsSplit), lds_rows, st, T, src, W, ctl);
+    hub_status s = launch_check("k_split_rows_fwd_ct");
+    if (s != HUB_OK) return s;
+    hipLaunchKernelGGL(k2, dim3(nrhs * c->Nt * (L / CB)), dim3(kThreadsSplit), lds_cols, st, T, W, ctl);
+    s = launch_check("k_split_cols_ct");
+    if (s != HUB_OK) return s;
+    hipLaunchKernelGGL(k3, dim3(nrow_blocks), dim3(kThreadsSplit), lds_rows, st, T, static_cast<const cx<R>*>(W),
+                       epi, ctl);
+    return launch_check("k_split_rows_inv_ct");
+}
+
 // Apply E between a source functor and an epilogue functor over nrhs right-hand sides.
 template <typename R, class Src, class Epi, class Ctl>
 hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ctl& ctl_in, hipStream_t st) {
@@ -185,6 +223,11 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
         case OpKind::Split:
         case OpKind::Linear:
             break;
+    }
+    if (c->specialized && c->L == 102) {
+        constexpr SplitGeom G102 = split_geom(102);
+        static_assert(102 % G102.rb == 0 && 102 % G102.cb == 0, "tiles must divide L");
+        return run_split_ct<R, 102, G102.rb, G102.cb>(c, nrhs, T, src, epi, ctl, st);
     }
     const SplitGeom G = split_geom(c->L);
     cx<R>* W = reinterpret_cast<cx<R>*>(c->split_w);

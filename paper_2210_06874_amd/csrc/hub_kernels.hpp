@@ -1057,6 +1057,175 @@ k_split_rows_inv(const OpTab<R> T, const SplitGeom G, const cx<R>* __restrict__ 
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
 }
 
+// ----------------------------------------------------------------------------- split, compile-time L
+// The three split kernels with L and the tile sizes known at compile time (both dividing L),
+// so the radix plan, the index arithmetic and the DFT coefficients are constants.  The tile
+// stages generalise ct_stage: line l of an LDS tile starts at (l / LG) * LGG + (l % LG) * LH
+// and its elements are ES apart; rows (ES = 1) give consecutive threads consecutive
+// butterflies of a line, columns give them consecutive lines.
+template <typename R, int L, int Q, bool INV, int NT, int NL, int LG, int LGG, int LH, int ES>
+__device__ __forceinline__ void ct_stage_tile(cx<R>* __restrict__ buf, const cx<R>* __restrict__ roots) {
+    constexpr CPlan P = make_cplan(L);
+    constexpr int RAD = P.radix[Q], LQ = P.len[Q], M = LQ / RAD, PER = L / RAD;
+    constexpr int NTASK = NL * PER, TWS = L / LQ, ST = M * ES;
+    for (int task = threadIdx.x; task < NTASK; task += NT) {
+        int line, j;
+        if constexpr (ES == 1) {
+            line = task / PER;
+            j = task - line * PER;
+        } else {
+            j = task / NL;
+            line = task - j * NL;
+        }
+        const int b = j / M, np = j - b * M;
+        const int lq = line / LG;
+        const int base = lq * LGG + (line - lq * LG) * LH + (b * LQ + np) * ES;
+        cx<R> x[RAD];
+#pragma unroll
+        for (int i = 0; i < RAD; ++i) x[i] = buf[base + i * ST];
+        if constexpr (!INV) {
+            small_dft_ct<R, RAD, false>(x);
+            if constexpr (M > 1) {
+#pragma unroll
+                for (int k = 1; k < RAD; ++k) x[k] = cmul(x[k], roots[np * k * TWS]);
+            }
+        } else {
+            if constexpr (M > 1) {
+#pragma unroll
+                for (int k = 1; k < RAD; ++k) x[k] = cmulc(x[k], roots[np * k * TWS]);
+            }
+            small_dft_ct<R, RAD, true>(x);
+        }
+#pragma unroll
+        for (int i = 0; i < RAD; ++i) buf[base + i * ST] = x[i];
+    }
+}
+
+template <typename R, int L, int Q, int QEND, int NT, int NL, int LG, int LGG, int LH, int ES>
+__device__ __forceinline__ void ct_forward_tile(cx<R>* buf, const cx<R>* roots) {
+    if constexpr (Q < QEND) {
+        ct_stage_tile<R, L, Q, false, NT, NL, LG, LGG, LH, ES>(buf, roots);
+        __syncthreads();
+        ct_forward_tile<R, L, Q + 1, QEND, NT, NL, LG, LGG, LH, ES>(buf, roots);
+    }
+}
+
+template <typename R, int L, int Q, int QLO, int NT, int NL, int LG, int LGG, int LH, int ES>
+__device__ __forceinline__ void ct_inverse_tile(cx<R>* buf, const cx<R>* roots) {
+    if constexpr (Q >= QLO) {
+        ct_stage_tile<R, L, Q, true, NT, NL, LG, LGG, LH, ES>(buf, roots);
+        __syncthreads();
+        ct_inverse_tile<R, L, Q - 1, QLO, NT, NL, LG, LGG, LH, ES>(buf, roots);
+    }
+}
+
+// (1) RB rows of one sublattice of the source slice, transformed, to the scratch vector W
+template <typename R, int L, int RB, int NT, class Src, class Ctl>
+__global__ void __launch_bounds__(NT)
+k_split_rows_fwd_ct(const OpTab<R> T, const Src src, cx<R>* __restrict__ W, const Ctl ctl) {
+    static_assert(L % RB == 0, "row blocks must tile the sublattice");
+    constexpr int NRB = L / RB;
+    constexpr CPlan P = make_cplan(L);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    cx<R>* roots = buf + RB * L;
+    int b = blockIdx.x;
+    const int rblk = b % NRB;
+    b /= NRB;
+    const int s = b % 2;
+    b /= 2;
+    const int t = b % T.Nt;
+    const int rhs = b / T.Nt;
+    const Scal sc = ctl.begin(rhs, -1, red_lds);
+    if (!sc.open) return;
+    for (int i = threadIdx.x; i < L; i += NT) roots[i] = T.roots[i];
+    const int ts = src.slice(t, T.Nt);
+    const int off = s * L * L + rblk * RB * L;
+    for (int i = threadIdx.x; i < RB * L; i += NT) buf[i] = src_apply(src, rhs, ts, off + i, T, sc);
+    __syncthreads();
+    ct_forward_tile<R, L, 0, P.nst, NT, RB, 1, L, 0, 1>(buf, roots);
+    cx<R>* dst = W + rhs * T.N + (long long)t * T.V + off;
+    for (int i = threadIdx.x; i < RB * L; i += NT) dst[i] = buf[i];
+}
+
+// (2) CB columns of both sublattices: column transforms, E(k), inverse column transforms, in W
+template <typename R, int L, int CB, int NT, class Ctl>
+__global__ void __launch_bounds__(NT)
+k_split_cols_ct(const OpTab<R> T, cx<R>* __restrict__ W, const Ctl ctl) {
+    static_assert(L % CB == 0, "column blocks must tile the sublattice");
+    constexpr int NCB = L / CB;
+    constexpr CPlan P = make_cplan(L);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    cx<R>* roots = buf + 2 * L * CB;
+    int b = blockIdx.x;
+    const int cblk = b % NCB;
+    b /= NCB;
+    const int t = b % T.Nt;
+    const int rhs = b / T.Nt;
+    const Scal sc = ctl.begin(rhs, -1, red_lds);
+    if (!sc.open) return;
+    const int c0 = cblk * CB;
+    for (int i = threadIdx.x; i < L; i += NT) roots[i] = T.roots[i];
+    cx<R>* base = W + rhs * T.N + (long long)t * T.V;
+    // LDS tile [s][n1][c], c fastest
+    for (int i = threadIdx.x; i < 2 * L * CB; i += NT) {
+        const int c = i % CB, sn = i / CB;           // sn = s*L + n1
+        buf[i] = base[(long long)sn * L + c0 + c];
+    }
+    __syncthreads();
+    ct_forward_tile<R, L, 0, P.nst, NT, 2 * CB, CB, L * CB, 1, CB>(buf, roots);
+    for (int i = threadIdx.x; i < L * CB; i += NT) {
+        const int c = i % CB, n1 = i / CB;
+        const int p = n1 * L + c0 + c;
+        const R cc = T.etab[4 * p], sr = T.etab[4 * p + 1], si = T.etab[4 * p + 2];
+        const cx<R> a = buf[i], bb = buf[L * CB + i];
+        buf[i] = {cc * a.re + sr * bb.re - si * bb.im, cc * a.im + sr * bb.im + si * bb.re};
+        buf[L * CB + i] = {cc * bb.re + sr * a.re + si * a.im, cc * bb.im + sr * a.im - si * a.re};
+    }
+    __syncthreads();
+    ct_inverse_tile<R, L, P.nst - 1, 0, NT, 2 * CB, CB, L * CB, 1, CB>(buf, roots);
+    for (int i = threadIdx.x; i < 2 * L * CB; i += NT) {
+        const int c = i % CB, sn = i / CB;
+        base[(long long)sn * L + c0 + c] = buf[i];
+    }
+}
+
+// (3) RB rows of W, inverse row transforms, and the epilogue
+template <typename R, int L, int RB, int NT, class Epi, class Ctl>
+__global__ void __launch_bounds__(NT)
+k_split_rows_inv_ct(const OpTab<R> T, const cx<R>* __restrict__ W, const Epi epi, const Ctl ctl) {
+    static_assert(L % RB == 0, "row blocks must tile the sublattice");
+    constexpr int NRB = L / RB;
+    constexpr CPlan P = make_cplan(L);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    cx<R>* roots = buf + RB * L;
+    int b = blockIdx.x;
+    const int slot = b % (2 * NRB * T.Nt);
+    const int rblk = b % NRB;
+    b /= NRB;
+    const int s = b % 2;
+    b /= 2;
+    const int t = b % T.Nt;
+    const int rhs = b / T.Nt;
+    const Scal sc = ctl.begin(rhs, slot, red_lds);
+    double acc = 0.0;
+    if (sc.open) {
+        for (int i = threadIdx.x; i < L; i += NT) roots[i] = T.roots[i];
+        const int off = s * L * L + rblk * RB * L;
+        const cx<R>* srcp = W + rhs * T.N + (long long)t * T.V + off;
+        for (int i = threadIdx.x; i < RB * L; i += NT) buf[i] = srcp[i];
+        __syncthreads();
+        ct_inverse_tile<R, L, P.nst - 1, 0, NT, RB, 1, L, 0, 1>(buf, roots);
+        for (int i = threadIdx.x; i < RB * L; i += NT) epi_apply(epi, rhs, t, off + i, buf[i], T, sc, acc);
+    }
+    if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
+}
+
 // ----------------------------------------------------------------------------- linear form
 // The fermion matrix as printed in Sec. 2, eq. "ferm_op" (linear in delta*kappa) is a
 // nearest-neighbour stencil in space and time: for destination (t, x)
