@@ -17,9 +17,11 @@ simulations of the Hubbard Model" (LATTICE2022):
   delta = beta/Nt.
 * Sec. 2, eq. "ferm_op": the fermion operator couples neighbouring time slices
   through e^{i delta phi} phases and hops between sublattices with strength
-  delta*kappa.  This oracle implements the exponential (transfer-matrix) form of
-  that operator: slice t couples to slice t-1 through exp(delta*kappa*K) times
+  delta*kappa.  HubbardOperator implements the exponential (transfer-matrix) form
+  of that operator: slice t couples to slice t-1 through exp(delta*kappa*K) times
   the phase diagonal of slice t-1, with an antiperiodic sign on the wrap.
+  LinearHubbardOperator implements the operator exactly as the equation prints it
+  (linear in delta*kappa, staggered between the sublattices).
 * Sec. 2: chi = M rho with rho ~ e^{-rho^dag rho}; the sampled weight is
   det(M M^dag) e^{-delta phi^2/(2U)}.
 
@@ -35,7 +37,10 @@ Conventions (readings where the paper is silent):
   det(M[phi,mu] M[phi,-mu]^dag).
 
 Functions carrying no independent pin say "parity unpinned" in their docstring;
-all others are pinned by the tests in tests/test_oracle_pins.py.
+all others are pinned by the tests in tests/test_oracle_pins.py (exponential form,
+chemical potential), tests/test_oracle_linear.py (linear form) and
+tests/test_oracle_hmc.py (trajectories), with planted mistakes in
+tests/test_oracle_mutants.py.
 """
 from __future__ import annotations
 
