@@ -32,18 +32,22 @@ def test_md_update_and_boson_energy_kernels():
     np.testing.assert_allclose(to_np(P), phi_ref, rtol=0, atol=1e-13 * np.abs(phi_ref).max())
 
 
+@pytest.mark.parametrize("integrator", ["leapfrog", "omelyan"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_trajectory_matches_oracle(prec):
+def test_trajectory_matches_oracle(prec, integrator):
     from paper_2210_06874_amd import hmc
     w = TINY
-    print(f"[case] hmc trajectory {prec} {w.name}", flush=True)
+    print(f"[case] hmc trajectory {prec} {integrator} {w.name}", flush=True)
     phi0 = draw_weak_field(w)[0]
     op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
     hub = _hub(w)
     for k, (pi, rho, u) in enumerate(draw_hmc_randoms(w, 3, seed=5)):
-        phi_ref, pi_ref, dH_ref, acc_ref, out_ref = OH.trajectory(op, w.U, phi0, pi, rho, u, n_md=8, eps=0.05)
+        phi_ref, pi_ref, dH_ref, acc_ref, out_ref = OH.trajectory(op, w.U, phi0, pi, rho, u, n_md=8, eps=0.05,
+                                                                  integrator=integrator)
         P = to_dev(phi0)
-        tr = hmc.trajectory(hub, P, w.U, to_dev(pi), to_dev(rho), u, n_md=8, eps=0.05, tol=1e-12, prec=prec)
+        tr = hmc.trajectory(hub, P, w.U, to_dev(pi), to_dev(rho), u, n_md=8, eps=0.05, tol=1e-12, prec=prec,
+                            integrator=integrator)
+        assert tr.n_forces == (9 if integrator == "leapfrog" else 17)
         assert abs(tr.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref)), (tr.dH, dH_ref)
         assert tr.accepted == acc_ref
         np.testing.assert_allclose(to_np(P), out_ref, atol=1e-8)

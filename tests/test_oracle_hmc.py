@@ -22,32 +22,36 @@ def _setup(form="exp"):
     return w, op, phi, pi, rho, u
 
 
+@pytest.mark.parametrize("integrator", ["leapfrog", "omelyan"])
 @pytest.mark.parametrize("form", ["exp", "linear"])
-def test_reversibility(form):
+def test_reversibility(form, integrator):
     """Integrate forward, flip the momentum, integrate back: the field returns."""
     w, op, phi, pi, rho, u = _setup(form)
     chi = op.apply_M(phi, rho)
-    phi1, pi1, dH, _, _ = OH.trajectory(op, w.U, phi, pi, rho, u, n_md=6, eps=0.05)
+    phi1, pi1, dH, _, _ = OH.trajectory(op, w.U, phi, pi, rho, u, n_md=6, eps=0.05, integrator=integrator)
     # backwards with the same chi: a trajectory from (phi1, -pi1) whose heat bath gives chi
     rho_back = np.linalg.solve(op.dense_M(phi1), chi.ravel()).reshape(rho.shape)
-    phi2, pi2, dH2, _, _ = OH.trajectory(op, w.U, phi1, -pi1, rho_back, u, n_md=6, eps=0.05)
+    phi2, pi2, dH2, _, _ = OH.trajectory(op, w.U, phi1, -pi1, rho_back, u, n_md=6, eps=0.05,
+                                         integrator=integrator)
     np.testing.assert_allclose(phi2, phi, atol=1e-9)
     np.testing.assert_allclose(-pi2, pi, atol=1e-9)
     assert abs(dH + dH2) < 1e-9
 
 
+@pytest.mark.parametrize("integrator", ["leapfrog", "omelyan"])
 @pytest.mark.parametrize("form", ["exp", "linear"])
-def test_energy_error_is_second_order(form):
-    """Leapfrog: dH(eps) ~ eps^2 at fixed trajectory length, so halving eps quarters dH.
-    A force that is not the gradient of H breaks this scaling.  (The linear form's
+def test_energy_error_is_second_order(form, integrator):
+    """Both integrators: dH(eps) ~ eps^2 at fixed trajectory length, so halving eps quarters
+    dH.  A force that is not the gradient of H breaks this scaling.  (The linear form's
     fourth-order term is larger on this field: its asymptotic regime starts at a shorter
     trajectory.)"""
     w, op, phi, pi, rho, u = _setup(form)
     dh = []
     T = 0.8 if form == "exp" else 0.4
-    for n in (16, 32, 64):
+    steps = (16, 32, 64) if integrator == "leapfrog" else (8, 16, 32)
+    for n in steps:
         eps = T / n
-        dh.append(abs(OH.trajectory(op, w.U, phi, pi, rho, u, n_md=n, eps=eps)[2]))
+        dh.append(abs(OH.trajectory(op, w.U, phi, pi, rho, u, n_md=n, eps=eps, integrator=integrator)[2]))
     r1, r2 = dh[0] / dh[1], dh[1] / dh[2]
     assert 3.3 < r1 < 4.7 and 3.6 < r2 < 4.4, (dh, r1, r2)
 
@@ -100,3 +104,32 @@ def test_creutz_equality_detects_a_wrong_heat_bath():
     Hamiltonian's distribution and <e^{-dH}> leaves 1 (by about 8 standard errors here)."""
     m, se = _creutz_chain("exp", rho_scale=math.sqrt(2.0))
     assert abs(m - 1.0) > 5 * se, (m, se)
+
+
+def test_omelyan_at_a_quarter_is_two_leapfrog_steps(monkeypatch):
+    """With lambda = 1/4 one Omelyan step of eps is exactly two leapfrog steps of eps/2
+    (the kicks eps/4, eps/2, eps/4 around two half drifts): the step sequence is pinned
+    against the leapfrog independently of the value of lambda."""
+    w, op, phi, pi, rho, u = _setup("exp")
+    monkeypatch.setattr(OH, "OMELYAN_LAMBDA", 0.25)
+    a = OH.trajectory(op, w.U, phi, pi, rho, u, n_md=5, eps=0.08, integrator="omelyan")
+    b = OH.trajectory(op, w.U, phi, pi, rho, u, n_md=10, eps=0.04)
+    np.testing.assert_allclose(a[0], b[0], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(a[1], b[1], rtol=0, atol=1e-12)
+    assert abs(a[2] - b[2]) < 1e-11
+
+
+def test_omelyan_lambda_is_the_minimum_norm_choice():
+    """The two-stage scheme's third-order error has coefficients (6 l^2 - 6 l + 1)/12 and
+    (1 - 6 l)/24 on its two nested commutators; the integrator's lambda minimises their
+    Euclidean norm."""
+    from scipy.optimize import minimize_scalar
+    f = lambda l: ((6 * l * l - 6 * l + 1) / 12) ** 2 + ((1 - 6 * l) / 24) ** 2
+    best = minimize_scalar(f, bounds=(0.0, 0.5), method="bounded", options={"xatol": 1e-13}).x
+    assert abs(best - OH.OMELYAN_LAMBDA) < 1e-8
+
+
+def test_unknown_integrator_is_refused():
+    w, op, phi, pi, rho, u = _setup("exp")
+    with pytest.raises(ValueError):
+        OH.trajectory(op, w.U, phi, pi, rho, u, n_md=2, eps=0.1, integrator="rk4")
