@@ -21,7 +21,10 @@ Also measured (not part of `value`):
     a nearest-neighbour stencil) and the roofline of its FP32 apply;
   * the CPU oracle (rank 0, N = 1 only) on a bounded sample of operator applications.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+`--stress` replaces all of this by the four-right-hand-side L = 102, Nt = 192 workload
+(operator launches for all four vectors, mixed CG iterations).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--stress]
 """
 from __future__ import annotations
 
@@ -192,6 +195,44 @@ def linear_leg(w, dev, P, C, P32, V32, out32, steps: int, warmup: int) -> dict:
     return out
 
 
+def stress_leg(dev, steps: int) -> dict:
+    """The four-right-hand-side L = 102, Nt = 192 workload (beta = 12, U = 3.9): one launch
+    applies M to all four vectors (FP32 and FP64), and a mixed-precision CG on the weak-field
+    input runs `steps` blocks of 50 iterations, all four right-hand sides in every launch."""
+    import torch
+    from paper_2210_06874_amd import Hubbard
+    from workloads import STRESS, draw_inputs, draw_weak_field
+    w = STRESS
+    phi, chi = draw_inputs(w, nrhs=w.nrhs)
+    P = torch.from_numpy(phi).to(dev)
+    C = torch.from_numpy(chi).to(dev)
+    P32, C32 = P.float(), C.to(torch.complex64)
+    o64, o32 = torch.empty_like(C), torch.empty_like(C32)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, nrhs_max=w.nrhs, device=dev)
+    t32 = time_graph(lambda: hub.apply_M_c64(P32, C32, out=o32), per_graph=10, replays=5)
+    t64 = time_graph(lambda: hub.apply_M(P, C, out=o64), per_graph=5, replays=4)
+    alg32, alg64 = 20.0 * w.N * w.nrhs, 40.0 * w.N * w.nrhs
+    pw, cw = draw_weak_field(w, nrhs=w.nrhs)
+    Pw, Cw = torch.from_numpy(pw).to(dev), torch.from_numpy(cw).to(dev)
+    n_it = 50 * max(1, steps)
+    hub.cg_solve(Pw, Cw, tol=1e-10, prec="mixed", max_iter=50, raise_on_error=False)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = hub.cg_solve(Pw, Cw, tol=1e-10, prec="mixed", max_iter=n_it, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = max(res.iters)
+    return {"workload": f"{w.name}: L={w.L} Nt={w.Nt} beta={w.beta} U={w.U}, {w.nrhs} right-hand sides per launch",
+            "apply_M_c64_us": t32 * 1e6, "apply_M_c64_GBs": alg32 / t32 / 1e9,
+            "apply_M_c64_hbm_frac": alg32 / t32 / 1e9 / HBM_PEAK_GBS,
+            "apply_M_us": t64 * 1e6, "apply_M_GBs": alg64 / t64 / 1e9,
+            "apply_M_hbm_frac": alg64 / t64 / 1e9 / HBM_PEAK_GBS,
+            "cg_mixed_us_per_iteration": dt / it * 1e6, "cg_iterations": it,
+            "cg_GBs": 96.0 * w.N * w.nrhs * it / dt / 1e9,
+            "timing": "operators: HIP graphs, events on their stream; CG: wall time of one solve "
+                      "(includes its reliable updates)"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +243,9 @@ def main() -> int:
                     help="CG iterations to time on the unscaled prior field (0: skip)")
     ap.add_argument("--probe", action="store_true",
                     help="only run 20 FP32 operator launches and a 64 MiB copy (for counter runs)")
+    ap.add_argument("--stress", action="store_true",
+                    help="instead of the force step: the four-right-hand-side L = 102, Nt = 192 "
+                         "workload (operator launches and mixed CG iterations), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the library runs on one GPU and this benchmark measures one GPU; "
@@ -234,6 +278,9 @@ def main() -> int:
             b.copy_(a)
         torch.cuda.synchronize()
         print("probe done")
+        return 0
+    if args.stress:
+        print(json.dumps(stress_leg(dev, args.steps)))
         return 0
     phi_w, chi_w = draw_weak_field(w)
     hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, device=dev)
