@@ -345,3 +345,38 @@ def test_output_buffers_are_checked():
     assert r3.data_ptr() == o3.data_ptr() and torch.equal(o3[0], ref)
     g = torch.empty_like(P)
     assert hub.force(P, V, out=g).data_ptr() == g.data_ptr()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_phase_accuracy_over_the_angle_range(prec):
+    """At kappa = 0 and v = 1, (M v)_t = 1 - B_t e^{i phi_{t-1}}, so the operator exposes every
+    phase it evaluates.  Angles from 1e-3 to 2e7, multiples of pi/2 and values on both sides
+    of the fast paths' limits (6,000 in FP32, 1e5 in FP64) must match e^{i phi} of the input
+    as given: FP64 to a few ulp, FP32 to the rounding of its argument reduction
+    (|phi| 2^-24 when |phi| < 6,000) plus the hardware sin/cos error."""
+    from paper_2210_06874_amd import Hubbard
+    w = Lattice("L3_Nt4", 3, 4, 1.0, 3.0, kappa=0.0)
+    rng = np.random.default_rng(41)
+    special = [0.0, np.pi / 2, -np.pi, 3 * np.pi / 2, 1e3 * np.pi, 5999.9, -6000.1, 6000.0,
+               99999.9, -100000.1, 1e5, 2e7, -2e7, 1234567.89]
+    mags = 10.0 ** rng.uniform(-3, 7.3, size=w.N - len(special))
+    phi = np.concatenate([special, mags * rng.choice([-1.0, 1.0], size=mags.size)]).reshape(w.Nt, w.V)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa)
+    B = np.ones(w.Nt)
+    B[0] = -1.0
+    if prec == "fp64":
+        out = to_np(hub.apply_M(to_dev(phi), torch.ones((w.Nt, w.V), dtype=torch.complex128, device=dev())))
+        ref_phi = phi
+    else:
+        p32 = phi.astype(np.float32)
+        out = to_np(hub.apply_M_c64(to_dev(p32), torch.ones((w.Nt, w.V), dtype=torch.complex64, device=dev())))
+        ref_phi = p32.astype(np.float64)
+    # (M 1)_t = 1 - B_t e^{i phi_{t-1}}  =>  e^{i phi_{t-1}} = B_t (1 - (M 1)_t)
+    got = np.roll(B[:, None] * (1.0 - out.astype(np.complex128)), -1, axis=0)
+    err = np.abs(got - np.exp(1j * ref_phi))
+    if prec == "fp64":
+        tol = np.full_like(err, 2e-15)
+    else:
+        tol = np.where(np.abs(ref_phi) < 6000.0, 2.0 * np.abs(ref_phi) * 2.0 ** -24, 0.0) + 1e-6
+    bad = np.argwhere(err > tol)
+    assert bad.size == 0, [(float(ref_phi[tuple(i)]), float(err[tuple(i)]), float(tol[tuple(i)])) for i in bad[:5]]
