@@ -208,3 +208,29 @@ def test_cg_free_plane_wave_at_scale(w, prec):
         ref = v / abs(lam) ** 2
         err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
         assert err <= 2 * cond * 1e-10, (n, m1, m2, err, cond)
+
+
+def test_cg_two_rhs_at_the_precision_workload():
+    """L = 51, N_t = 128 with two right-hand sides: the iteration kernels run one workgroup
+    per slice (one right-hand side runs two per slice, with twice the reduction slots).  Both
+    solves meet tol on the oracle's own FP64 residual, and agree with one-rhs solves to within
+    the conditioning."""
+    from workloads import draw_weak_field
+    w = PREC
+    print(f"[case] cg two rhs {w.name}", flush=True)
+    phi, chi = draw_weak_field(w, seed=3, nrhs=2)
+    op = oracle_op(w, mode="expm")
+    hub2 = _hub(w, nrhs=2)
+    res = hub2.cg_solve(to_dev(phi), to_dev(chi), tol=1e-10, prec="mixed")
+    assert res.converged, (res.true_rel_res, res.iters)
+    x2 = to_np(res.x)
+    r = chi - op.apply_A(phi, x2)
+    hub1 = _hub(w, nrhs=1)
+    for k in range(2):
+        rel = np.linalg.norm(r[k]) / np.linalg.norm(chi[k])
+        assert rel <= 2e-10, (k, rel)
+        one = hub1.cg_solve(to_dev(phi), to_dev(chi[k:k + 1]), tol=1e-10, prec="mixed")
+        assert one.converged
+        x1 = to_np(one.x)[0]
+        assert np.linalg.norm(x2[k] - x1) <= 1e-5 * np.linalg.norm(x1)
+        assert abs(res.iters[k] - one.iters[0]) <= 0.05 * one.iters[0]
