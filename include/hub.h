@@ -48,6 +48,10 @@
  *
  * Threads: a context may be used from one host thread at a time.  Calls on one
  * context that overlap in time (on different streams) share its workspace and race.
+ *
+ * Devices: a context belongs to the device that was current at hub_create; every
+ * later call must be made with that device current (HUB_ERR_ARG otherwise), except
+ * hub_destroy, which switches to it by itself.
  */
 #ifndef HUB_H
 #define HUB_H

@@ -277,6 +277,16 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 // in: nrhs vectors of `elem`-byte entries; out: nrhs vectors (out_per_rhs) or one array of
 // N entries of out_elem bytes; phi: N entries of phi_elem bytes.  The output may overlap
 // neither input (other workgroups still read them while it is written).
+// Every call runs on the current device, which must be the one the context was created on
+// (its tables, scratch and the caller's arrays live there).
+hub_status check_device(const hub_ctx* c) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(HUB_ERR_DEVICE, "hipGetDevice failed");
+    if (dev != c->device)
+        return fail(HUB_ERR_ARG, "the context lives on device %d but device %d is current", c->device, dev);
+    return HUB_OK;
+}
+
 hub_status check_vec_args(const hub_ctx* c, const void* phi, const void* in, const void* out, int nrhs,
                           size_t elem, size_t out_elem, bool out_per_rhs, size_t phi_elem) {
     if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
@@ -287,7 +297,7 @@ hub_status check_vec_args(const hub_ctx* c, const void* phi, const void* in, con
     const size_t out_bytes = (size_t)(out_per_rhs ? nrhs : 1) * c->N * out_elem;
     if (overlaps(in, in_bytes, out, out_bytes)) return fail(HUB_ERR_ARG, "input and output overlap");
     if (overlaps(phi, (size_t)c->N * phi_elem, out, out_bytes)) return fail(HUB_ERR_ARG, "phi and output overlap");
-    return HUB_OK;
+    return check_device(c);
 }
 
 template <typename R>
@@ -638,6 +648,9 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
 
 void hub_destroy(hub_ctx* c) {
     if (!c) return;
+    int prev = -1;
+    const bool switched = hipGetDevice(&prev) == hipSuccess && prev != c->device &&
+                          hipSetDevice(c->device) == hipSuccess;
     (void)hipDeviceSynchronize();
     void* dev[] = {c->roots64, c->roots32, c->etab64, c->etab32, c->partials, c->counters, c->red_out,
                    c->split_w, c->cg_rhi, c->cg_tmp, c->cg_x, c->cg_r, c->cg_p, c->cg_t,
@@ -647,6 +660,7 @@ void hub_destroy(hub_ctx* c) {
     if (c->scal_host) (void)hipHostFree(c->scal_host);
     if (c->cg_event) (void)hipEventDestroy(c->cg_event);
     delete c;
+    if (switched) (void)hipSetDevice(prev);
 }
 
 hub_status hub_apply_M(hub_ctx* c, const double* phi, const void* in, void* out, int32_t nrhs, void* st) {
@@ -704,6 +718,7 @@ hub_status hub_action(hub_ctx* c, const void* chi, const void* x, int32_t nrhs, 
     if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
     if (!chi || !x || !S_dev) return fail(HUB_ERR_ARG, "NULL array argument");
     if (nrhs < 1 || nrhs > c->nrhs_max) return fail(HUB_ERR_ARG, "nrhs=%d outside [1, %d]", nrhs, c->nrhs_max);
+    if (hub_status d = check_device(c); d != HUB_OK) return d;
     hipStream_t st = static_cast<hipStream_t>(stream);
     RedArgs ra{c->partials, c->counters + 6, c->Nt, nrhs};
     hipLaunchKernelGGL(k_dot_re, dim3(nrhs * c->Nt), dim3(kThreads), 0, st, static_cast<const cx<double>*>(chi),
@@ -720,6 +735,7 @@ hub_status hub_md_update(hub_ctx* c, double* phi, double* pi, const double* dSdp
     const size_t bytes = (size_t)c->N * sizeof(double);
     if (overlaps(phi, bytes, pi, bytes) || overlaps(phi, bytes, dSdphi, bytes) || overlaps(pi, bytes, dSdphi, bytes))
         return fail(HUB_ERR_ARG, "phi, pi and dSdphi must not overlap");
+    if (hub_status d = check_device(c); d != HUB_OK) return d;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_md_update, dim3(1024), dim3(kThreads), 0, st, phi, pi, dSdphi, c->N, 1.0 / (c->delta * U),
                        eps_pi, eps_phi);
@@ -731,6 +747,7 @@ hub_status hub_boson_energy(hub_ctx* c, const double* phi, const double* pi, dou
     if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
     if (!phi || !pi || !out_dev) return fail(HUB_ERR_ARG, "NULL array argument");
     if (!(U > 0.0) || !std::isfinite(U)) return fail(HUB_ERR_ARG, "U must be > 0");
+    if (hub_status d = check_device(c); d != HUB_OK) return d;
     hipStream_t st = static_cast<hipStream_t>(stream);
     RedArgs ra{c->partials, c->counters + 7, c->Nt, 1};
     hipLaunchKernelGGL(k_boson_energy, dim3(c->Nt), dim3(kThreads), 0, st, phi, pi, c->V, 1.0 / (c->delta * U),
