@@ -36,7 +36,8 @@
  * owned by the caller; the library keeps no pointer after a call returns.  The
  * context owns its tables and workspace: hub_create allocates the tables, the
  * reduction partials and the operator scratch, the first hub_cg_solve the solver
- * vectors; nothing else allocates; hub_destroy frees all of it.
+ * vectors, the first hub_trajectory its own vectors; nothing else allocates;
+ * hub_destroy frees all of it.
  *
  * Streams: every call enqueues its work on `stream` (a hipStream_t; NULL means
  * the default stream) and returns without synchronising, except hub_cg_solve,
@@ -183,6 +184,38 @@ hub_status hub_md_update(hub_ctx* ctx, double* phi, double* pi, const double* dS
  * Hamiltonian of eq. "hamiltonian" (its fermionic part is hub_action).  One double on the device. */
 hub_status hub_boson_energy(hub_ctx* ctx, const double* phi, const double* pi, double U, double* out_dev,
                             void* stream);
+
+/* Molecular-dynamics integrators of hub_trajectory. */
+typedef enum { HUB_MD_LEAPFROG = 0, HUB_MD_OMELYAN = 1 } hub_integrator;
+
+typedef struct {
+    double U;               /* on-site coupling of the Gaussian term phi^2/(2 delta U), > 0        */
+    double eps;             /* molecular-dynamics step, > 0                                         */
+    int32_t n_md;           /* steps per trajectory, >= 1                                           */
+    int32_t integrator;     /* hub_integrator: leapfrog (n_md + 1 forces) or the second-order
+                               minimum-norm scheme of Omelyan, Mryglod and Folk (2 n_md + 1)         */
+    hub_cg_opts cg;         /* every solve of the trajectory; use_x0 is ignored (the first solve
+                               starts from 0, the others from the previous solution)               */
+} hub_traj_opts;
+
+typedef struct {
+    int32_t accepted;       /* 1: phi holds the end of the trajectory; 0: phi was restored          */
+    int32_t n_forces;       /* force evaluations (= CG solves after the first)                      */
+    int32_t cg_iters;       /* CG iterations over all solves, largest right-hand side count each    */
+    double H0, H1, dH;      /* Hamiltonian at the start and end (FP64), dH = H1 - H0                */
+} hub_traj_info;
+
+/* One HMC trajectory (Sec. 2) on the device: heat bath chi = M[phi] rho for nrhs
+ * pseudofermions, molecular dynamics of H = pi^2/2 + phi^2/(2 delta U) + sum_r chi_r^dag
+ * (M M^dag)^{-1} chi_r with the adjoint force, and the Metropolis decision: accepted when
+ * dH <= 0 or u < e^{-dH}.  phi (double [Nt][V]) is updated in place and restored when the
+ * trajectory is rejected or a solve fails (the status of that solve is returned).  pi0
+ * (double [Nt][V]) and rho (complex128 [nrhs][Nt][V]) are inputs on the device, not
+ * overlapping phi; u is the uniform deviate of the decision.  The random numbers are the
+ * caller's: the library draws none.  The first call allocates the trajectory's vectors in
+ * the context; the call synchronises on `stream` (each solve reads its status). */
+hub_status hub_trajectory(hub_ctx* ctx, double* phi, const double* pi0, const void* rho, int32_t nrhs,
+                          double u, const hub_traj_opts* opts, hub_traj_info* info_host, void* stream);
 
 /* Report the kernel path the context uses (hub_path value, never AUTO) and the
  * LDS bytes per workgroup of its operator kernel (HUB_FORM_LINEAR: FUSED and 0, one

@@ -22,6 +22,7 @@ _PREC = {"fp64": _lib.HUB_PREC_FP64, "mixed": _lib.HUB_PREC_MIXED}
 _PATH = {"auto": _lib.HUB_PATH_AUTO, "fused": _lib.HUB_PATH_FUSED, "split": _lib.HUB_PATH_SPLIT}
 _PATH_NAME = {v: k for k, v in _PATH.items()}
 _FORM = {"exp": _lib.HUB_FORM_EXP, "linear": _lib.HUB_FORM_LINEAR}
+_INTEGRATOR = {"leapfrog": _lib.HUB_MD_LEAPFROG, "omelyan": _lib.HUB_MD_OMELYAN}
 
 
 def _stream_ptr(device) -> ctypes.c_void_p:
@@ -210,6 +211,22 @@ class Hubbard:
             _lib.check(self.lib.hub_boson_energy(self._h, self._p(phi), self._p(pi), float(U), self._p(E),
                                                  _stream_ptr(self.device)))
         return E
+
+    def trajectory(self, phi, pi0, rho, u: float, U: float, n_md: int, eps: float,
+                   integrator: str = "leapfrog", tol: float = 1e-10, prec: str = "mixed",
+                   max_iter: int = 200000, reliable_every: int = 50) -> "_lib.HubTrajInfo":
+        """One HMC trajectory (hub_trajectory): phi is updated in place, or left as it was
+        when the trajectory is rejected.  rho: complex128 [nrhs, Nt, V] or [Nt, V]."""
+        self._phi(phi)
+        self._phi(pi0)
+        rho3, nrhs = self._vec(rho, name="rho")
+        opts = _lib.HubTrajOpts(float(U), float(eps), int(n_md), _INTEGRATOR[integrator],
+                                _lib.HubCgOpts(float(tol), int(max_iter), int(reliable_every), _PREC[prec], 0, 0))
+        info = _lib.HubTrajInfo()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_trajectory(self._h, self._p(phi), self._p(pi0), self._p(rho3), nrhs, float(u),
+                                               ctypes.byref(opts), ctypes.byref(info), _stream_ptr(self.device)))
+        return info
 
 
 from .autograd import PseudofermionAction  # noqa: E402

@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_DEVICE", 3: "HUB_ERR_
 HUB_PREC_FP64, HUB_PREC_MIXED = 0, 1
 HUB_PATH_AUTO, HUB_PATH_FUSED, HUB_PATH_SPLIT = 0, 1, 2
 HUB_FORM_EXP, HUB_FORM_LINEAR = 0, 1
+HUB_MD_LEAPFROG, HUB_MD_OMELYAN = 0, 1
 
 
 class HubParams(ctypes.Structure):
@@ -32,6 +33,16 @@ class HubCgInfo(ctypes.Structure):
                 ("true_rel_res", ctypes.c_double), ("recursive_rel_res", ctypes.c_double)]
 
 
+class HubTrajOpts(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_double), ("eps", ctypes.c_double), ("n_md", ctypes.c_int32),
+                ("integrator", ctypes.c_int32), ("cg", HubCgOpts)]
+
+
+class HubTrajInfo(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int32), ("n_forces", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("H0", ctypes.c_double), ("H1", ctypes.c_double), ("dH", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 SIGNATURES = {
@@ -46,6 +57,8 @@ SIGNATURES = {
     "hub_action": (_P, _P, _P, _I, _P, _P),
     "hub_md_update": (_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P),
     "hub_boson_energy": (_P, _P, _P, ctypes.c_double, _P, _P),
+    "hub_trajectory": (_P, _P, _P, _P, _I, ctypes.c_double, ctypes.POINTER(HubTrajOpts),
+                       ctypes.POINTER(HubTrajInfo), _P),
     "hub_query": (_P, ctypes.POINTER(_I), ctypes.POINTER(_I)),
     "hub_last_error": (),
 }

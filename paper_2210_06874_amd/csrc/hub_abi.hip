@@ -18,6 +18,8 @@ namespace {
 #define HUB_THREADS_51 512
 #endif
 constexpr int kThreads51 = HUB_THREADS_51;   // workgroup size of the L = 51 kernels
+// the minimum-norm choice of the Omelyan-Mryglod-Folk second-order integrator
+constexpr double kOmelyanLambda = 0.1931833275037836;
 #ifndef HUB_HALF_BELOW
 #define HUB_HALF_BELOW 256
 #endif
@@ -654,10 +656,12 @@ void hub_destroy(hub_ctx* c) {
     (void)hipDeviceSynchronize();
     void* dev[] = {c->roots64, c->roots32, c->etab64, c->etab32, c->partials, c->counters, c->red_out,
                    c->split_w, c->cg_rhi, c->cg_tmp, c->cg_x, c->cg_r, c->cg_p, c->cg_t,
-                   c->ph64, c->ph32, c->scal, c->cg_pr, c->cg_pt, c->force_tmp};
+                   c->ph64, c->ph32, c->scal, c->cg_pr, c->cg_pt, c->force_tmp,
+                   c->tr_chi, c->tr_x, c->tr_pi, c->tr_phi0, c->tr_g, c->tr_E};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->scal_host) (void)hipHostFree(c->scal_host);
+    if (c->tr_E_host) (void)hipHostFree(c->tr_E_host);
     if (c->cg_event) (void)hipEventDestroy(c->cg_event);
     delete c;
     if (switched) (void)hipSetDevice(prev);
@@ -753,6 +757,119 @@ hub_status hub_boson_energy(hub_ctx* c, const double* phi, const double* pi, dou
     hipLaunchKernelGGL(k_boson_energy, dim3(c->Nt), dim3(kThreads), 0, st, phi, pi, c->V, 1.0 / (c->delta * U),
                        FinStore{out_dev, 1}, ra);
     return launch_check("k_boson_energy");
+}
+
+hub_status hub_trajectory(hub_ctx* c, double* phi, const double* pi0, const void* rho, int32_t nrhs, double u,
+                          const hub_traj_opts* o, hub_traj_info* info, void* stream) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (!phi || !pi0 || !rho || !o) return fail(HUB_ERR_ARG, "NULL argument");
+    if (nrhs < 1 || nrhs > c->nrhs_max) return fail(HUB_ERR_ARG, "nrhs=%d outside [1, %d]", nrhs, c->nrhs_max);
+    if (!(o->U > 0.0) || !std::isfinite(o->U) || !(o->eps > 0.0) || !std::isfinite(o->eps) || o->n_md < 1)
+        return fail(HUB_ERR_ARG, "U and eps must be finite and > 0, n_md >= 1");
+    if (o->integrator != HUB_MD_LEAPFROG && o->integrator != HUB_MD_OMELYAN)
+        return fail(HUB_ERR_ARG, "bad integrator %d", o->integrator);
+    if (!std::isfinite(u)) return fail(HUB_ERR_ARG, "u must be finite");
+    const size_t fb = (size_t)c->N * sizeof(double), vb = (size_t)nrhs * c->N * sizeof(cx<double>);
+    if (overlaps(phi, fb, pi0, fb) || overlaps(phi, fb, rho, vb)) return fail(HUB_ERR_ARG, "phi overlaps pi0 or rho");
+    if (hub_status d = check_device(c); d != HUB_OK) return d;
+    // workspace, kept by the context (a failed allocation leaves the others for the next call)
+    const size_t wb = (size_t)c->nrhs_max * c->N * sizeof(cx<double>);
+    struct Need {
+        void** p;
+        size_t bytes;
+    } need[] = {{&c->tr_chi, wb}, {&c->tr_x, wb}, {reinterpret_cast<void**>(&c->tr_pi), fb},
+                {reinterpret_cast<void**>(&c->tr_phi0), fb}, {reinterpret_cast<void**>(&c->tr_g), fb},
+                {reinterpret_cast<void**>(&c->tr_E), 2 * sizeof(double)}};
+    for (const Need& n : need)
+        if (!*n.p) HIP_OR_FAIL(hipMalloc(n.p, n.bytes));
+    if (!c->tr_E_host)
+        HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void**>(&c->tr_E_host), 2 * sizeof(double), hipHostMallocDefault));
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    cx<double>* chi = static_cast<cx<double>*>(c->tr_chi);
+    cx<double>* x = static_cast<cx<double>*>(c->tr_x);
+    double* pi = c->tr_pi;
+    double* g = c->tr_g;
+    HIP_OR_FAIL(hipMemcpyAsync(c->tr_phi0, phi, fb, hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(hipMemcpyAsync(pi, pi0, fb, hipMemcpyDeviceToDevice, st));
+    bool restore = true;              // until the decision, a failure puts the start field back
+    auto finish = [&](hub_status status) -> hub_status {
+        if (restore) (void)hipMemcpyAsync(phi, c->tr_phi0, fb, hipMemcpyDeviceToDevice, st);
+        const hipError_t e = hipStreamSynchronize(st);
+        if (status == HUB_OK && e != hipSuccess)
+            return fail(HUB_ERR_DEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+        return status;
+    };
+
+    hub_status s = hub_apply_M(c, phi, rho, chi, nrhs, stream);     // heat bath chi = M rho
+    if (s != HUB_OK) return finish(s);
+    hub_cg_opts cg = o->cg;
+    std::vector<hub_cg_info> ci(nrhs);
+    int iters = 0, n_forces = 0;
+    auto solve = [&](int use_x0) -> hub_status {
+        cg.use_x0 = use_x0;
+        const hub_status r = hub_cg_solve(c, phi, chi, x, nrhs, &cg, ci.data(), stream);
+        int m = 0;
+        for (const hub_cg_info& i : ci) m = std::max(m, (int)i.iters);
+        iters += m;
+        return r;
+    };
+    auto energy = [&](double* H) -> hub_status {
+        hub_status r = hub_boson_energy(c, phi, pi, o->U, c->tr_E, stream);
+        if (r != HUB_OK) return r;
+        r = hub_action(c, chi, x, nrhs, c->tr_E + 1, stream);
+        if (r != HUB_OK) return r;
+        HIP_OR_FAIL(hipMemcpyAsync(c->tr_E_host, c->tr_E, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(hipStreamSynchronize(st));
+        *H = c->tr_E_host[0] + c->tr_E_host[1];
+        return HUB_OK;
+    };
+    // solve at the current field, then the force and one update (eps_pi, eps_phi)
+    auto kick = [&](bool warm, double eps_pi, double eps_phi) -> hub_status {
+        if (warm) {
+            const hub_status r = solve(1);
+            if (r != HUB_OK) return r;
+        }
+        hub_status r = hub_force(c, phi, x, g, nrhs, stream);
+        if (r != HUB_OK) return r;
+        ++n_forces;
+        return hub_md_update(c, phi, pi, g, o->U, eps_pi, eps_phi, stream);
+    };
+
+    s = solve(0);
+    if (s != HUB_OK) return finish(s);
+    double H0 = 0.0, H1 = 0.0;
+    s = energy(&H0);
+    if (s != HUB_OK) return finish(s);
+    const double eps = o->eps;
+    const int n = o->n_md;
+    if (o->integrator == HUB_MD_LEAPFROG) {
+        s = kick(false, 0.5 * eps, eps);
+        for (int k = 1; k <= n && s == HUB_OK; ++k)
+            s = k < n ? kick(true, eps, eps) : kick(true, 0.5 * eps, 0.0);
+    } else {
+        const double lam = kOmelyanLambda;
+        s = kick(false, lam * eps, 0.5 * eps);
+        for (int k = 1; k <= n && s == HUB_OK; ++k) {
+            s = kick(true, (1.0 - 2.0 * lam) * eps, 0.5 * eps);
+            if (s == HUB_OK) s = k < n ? kick(true, 2.0 * lam * eps, 0.5 * eps) : kick(true, lam * eps, 0.0);
+        }
+    }
+    if (s != HUB_OK) return finish(s);
+    s = energy(&H1);
+    if (s != HUB_OK) return finish(s);
+    const double dH = H1 - H0;
+    const bool accepted = dH <= 0.0 || u < std::exp(-dH);
+    restore = !accepted;
+    if (info) {
+        info->accepted = accepted ? 1 : 0;
+        info->n_forces = n_forces;
+        info->cg_iters = iters;
+        info->H0 = H0;
+        info->H1 = H1;
+        info->dH = dH;
+    }
+    return finish(HUB_OK);
 }
 
 hub_status hub_query(const hub_ctx* c, int32_t* path, int32_t* lds_bytes) {

@@ -76,5 +76,13 @@ struct hub_ctx {
     double* cg_pt = nullptr;             // ||M^dag p||^2 partials, [nrhs_max][max_partials]
     hub::CgScalars* scal_host = nullptr; // pinned host mirror
     hipEvent_t cg_event = nullptr;       // marks the copy of the scalars into scal_host
+    // HMC trajectory workspace (allocated on the first trajectory)
+    void* tr_chi = nullptr;              // complex128 [nrhs_max][N]: the pseudofermions
+    void* tr_x = nullptr;                // complex128 [nrhs_max][N]: the solutions
+    double* tr_pi = nullptr;             // [N] momenta
+    double* tr_phi0 = nullptr;           // [N] the field at the start
+    double* tr_g = nullptr;              // [N] dS_f/dphi
+    double* tr_E = nullptr;              // [2] device: boson energy, action
+    double* tr_E_host = nullptr;         // [2] pinned mirror
     double* force_tmp = nullptr;         // [nrhs_max][N] doubles, per-rhs force before summation (hub_create)
 };

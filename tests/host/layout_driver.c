@@ -15,5 +15,11 @@ int main(void) {
     printf("hub_cg_info %zu %zu %zu %zu %zu\n", sizeof(hub_cg_info), offsetof(hub_cg_info, iters),
            offsetof(hub_cg_info, reliable_updates), offsetof(hub_cg_info, true_rel_res),
            offsetof(hub_cg_info, recursive_rel_res));
+    printf("hub_traj_opts %zu %zu %zu %zu %zu %zu\n", sizeof(hub_traj_opts), offsetof(hub_traj_opts, U),
+           offsetof(hub_traj_opts, eps), offsetof(hub_traj_opts, n_md), offsetof(hub_traj_opts, integrator),
+           offsetof(hub_traj_opts, cg));
+    printf("hub_traj_info %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hub_traj_info), offsetof(hub_traj_info, accepted),
+           offsetof(hub_traj_info, n_forces), offsetof(hub_traj_info, cg_iters), offsetof(hub_traj_info, H0),
+           offsetof(hub_traj_info, H1), offsetof(hub_traj_info, dH));
     return 0;
 }

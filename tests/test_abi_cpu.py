@@ -43,7 +43,8 @@ def test_struct_layouts_match_the_binding(tmp_path):
                     os.path.join(ROOT, "tests", "host", "layout_driver.c"), "-o", str(exe)], check=True)
     lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines()
     got = {ln.split()[0]: list(map(int, ln.split()[1:])) for ln in lines}
-    for cname, cls in (("hub_params", L.HubParams), ("hub_cg_opts", L.HubCgOpts), ("hub_cg_info", L.HubCgInfo)):
+    for cname, cls in (("hub_params", L.HubParams), ("hub_cg_opts", L.HubCgOpts), ("hub_cg_info", L.HubCgInfo),
+                       ("hub_traj_opts", L.HubTrajOpts), ("hub_traj_info", L.HubTrajInfo)):
         ref = [ctypes.sizeof(cls)] + [getattr(cls, f[0]).offset for f in cls._fields_]
         assert got[cname] == ref, (cname, got[cname], ref)
 
@@ -72,6 +73,8 @@ def test_argument_errors_before_any_device_call():
     opts = L.HubCgOpts(1e-10, 100, 50, 0, 0)
     assert lib.hub_cg_solve(None, x, x, x, 1, ctypes.byref(opts), None, None) == L.HUB_ERR_ARG
     assert lib.hub_query(None, None, None) == L.HUB_ERR_ARG
+    topts = L.HubTrajOpts(3.0, 0.1, 4, 0, opts)
+    assert lib.hub_trajectory(None, x, x, x, 1, 0.5, ctypes.byref(topts), None, None) == L.HUB_ERR_ARG
     lib.hub_destroy(None)   # no-op
 
 

@@ -107,3 +107,46 @@ def test_markov_chain_matches_oracle_chain(form):
         np.testing.assert_allclose(to_np(P), phi_ref, rtol=0, atol=1e-8, err_msg=f"trajectory {k}")
         decisions.append(acc_ref)
     assert 0 < decisions.count(False) < 30     # the chain both accepts and rejects
+
+
+def test_two_pseudofermion_trajectory_matches_oracle():
+    """hub_trajectory with two pseudofermions (the action and force summed over both)."""
+    from paper_2210_06874_amd import Hubbard, hmc
+    w = TINY
+    print(f"[case] hmc trajectory two pseudofermions {w.name}", flush=True)
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, nrhs_max=2)
+    phi0 = draw_weak_field(w)[0]
+    for k, (pi, rho, u) in enumerate(draw_hmc_randoms(w, 2, seed=8, nrhs=2)):
+        _, _, dH_ref, acc_ref, out_ref = OH.trajectory(op, w.U, phi0, pi, rho, u, n_md=6, eps=0.05,
+                                                       integrator="omelyan")
+        P = to_dev(phi0)
+        tr = hmc.trajectory(hub, P, w.U, to_dev(pi), to_dev(rho), u, n_md=6, eps=0.05, tol=1e-12, prec="fp64",
+                            integrator="omelyan")
+        assert abs(tr.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref)), (k, tr.dH, dH_ref)
+        assert tr.accepted == acc_ref and tr.n_forces == 13 and tr.cg_iters > 0
+        np.testing.assert_allclose(to_np(P), out_ref, atol=1e-8)
+        phi0 = out_ref
+
+
+def test_failed_trajectory_restores_the_field():
+    """A solve that cannot meet tol within max_iter ends the trajectory with HUB_ERR_NOCONV
+    and leaves phi exactly as it was; a rejected trajectory does the same."""
+    from paper_2210_06874_amd import HubError
+    from paper_2210_06874_amd._lib import HUB_ERR_NOCONV
+    w = TINY
+    hub = _hub(w)
+    phi0 = draw_weak_field(w)[0]
+    (pi, rho, u), = draw_hmc_randoms(w, 1, seed=9)
+    P = to_dev(phi0)
+    with pytest.raises(HubError) as e:
+        hub.trajectory(P, to_dev(pi), to_dev(rho), u, w.U, n_md=4, eps=0.05, tol=1e-14, max_iter=3)
+    assert e.value.status == HUB_ERR_NOCONV
+    assert np.array_equal(to_np(P), phi0)
+    # a coarse step (dH of several units): rejected at u = 0.999, phi untouched
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+    dH_ref = OH.trajectory(op, w.U, phi0, pi, rho, 0.999, n_md=4, eps=0.2)[2]
+    assert dH_ref > 1.0
+    info = hub.trajectory(P, to_dev(pi), to_dev(rho), 0.999, w.U, n_md=4, eps=0.2, tol=1e-12, prec="fp64")
+    assert info.accepted == 0 and abs(info.dH - dH_ref) < 1e-7 * dH_ref, (info.dH, dH_ref)
+    assert np.array_equal(to_np(P), phi0)
