@@ -2,11 +2,15 @@
  * from a binary file, runs M chi, a mixed-precision CG solve and the force on the current
  * HIP device, and writes M chi, x and dS/dphi to a binary file.
  *
- *   abi_driver L Nt beta kappa form in.bin out.bin
+ *   abi_driver L Nt beta kappa form in.bin out.bin [U eps n_md u]
  *
- * in.bin : phi (Nt*V doubles), chi (Nt*V complex doubles, interleaved)
+ * in.bin : phi (Nt*V doubles), chi (Nt*V complex doubles, interleaved), and with the
+ *          trajectory arguments the momenta pi0 (Nt*V doubles)
  * out.bin: M chi (Nt*V complex), x (Nt*V complex), dSdphi (Nt*V doubles), then the CG
- *          iteration count and true relative residual (int32, double)
+ *          iteration count and true relative residual (int32, double); with the trajectory
+ *          arguments also one leapfrog HMC trajectory from (phi, pi0) with heat-bath vector
+ *          rho = chi, uniform deviate u and solves to 1e-12: accepted (int32), dH (double), phi after it
+ *          (Nt*V doubles)
  * Exit status 0 on success, 1 on a library or runtime error (message on stderr). */
 #include <stdio.h>
 #include <stdlib.h>
@@ -34,10 +38,11 @@
     } while (0)
 
 int main(int argc, char** argv) {
-    if (argc != 8) {
-        fprintf(stderr, "usage: %s L Nt beta kappa form in.bin out.bin\n", argv[0]);
+    if (argc != 8 && argc != 12) {
+        fprintf(stderr, "usage: %s L Nt beta kappa form in.bin out.bin [U eps n_md u]\n", argv[0]);
         return 1;
     }
+    const int traj = argc == 12;
     hub_params prm = {0};
     prm.L = atoi(argv[1]);
     prm.Nt = atoi(argv[2]);
@@ -51,10 +56,12 @@ int main(int argc, char** argv) {
 
     double* phi = malloc(N * sizeof(double));
     double* chi = malloc(2 * N * sizeof(double));
-    double* out = malloc(5 * N * sizeof(double));
-    if (!phi || !chi || !out) return 1;
+    double* out = malloc(6 * N * sizeof(double));
+    double* pi0 = malloc(N * sizeof(double));
+    if (!phi || !chi || !out || !pi0) return 1;
     FILE* f = fopen(argv[6], "rb");
-    if (!f || fread(phi, sizeof(double), N, f) != N || fread(chi, sizeof(double), 2 * N, f) != 2 * N) {
+    if (!f || fread(phi, sizeof(double), N, f) != N || fread(chi, sizeof(double), 2 * N, f) != 2 * N ||
+        (traj && fread(pi0, sizeof(double), N, f) != N)) {
         fprintf(stderr, "cannot read %s\n", argv[6]);
         return 1;
     }
@@ -89,6 +96,22 @@ int main(int argc, char** argv) {
     CHECK_HIP(hipMemcpy(out, d_mv, 2 * N * sizeof(double), hipMemcpyDeviceToHost));
     CHECK_HIP(hipMemcpy(out + 2 * N, d_x, 2 * N * sizeof(double), hipMemcpyDeviceToHost));
     CHECK_HIP(hipMemcpy(out + 4 * N, d_g, N * sizeof(double), hipMemcpyDeviceToHost));
+    hub_traj_info tinfo = {0};
+    if (traj) {
+        double* d_pi;
+        CHECK_HIP(hipMalloc((void**)&d_pi, N * sizeof(double)));
+        CHECK_HIP(hipMemcpy(d_pi, pi0, N * sizeof(double), hipMemcpyHostToDevice));
+        hub_traj_opts to = {0};
+        to.U = atof(argv[8]);
+        to.eps = atof(argv[9]);
+        to.n_md = atoi(argv[10]);
+        to.integrator = HUB_MD_LEAPFROG;
+        to.cg = opts;
+        to.cg.tol = 1e-12;
+        CHECK_HUB(hub_trajectory(ctx, d_phi, d_pi, d_chi, 1, atof(argv[11]), &to, &tinfo, st));
+        CHECK_HIP(hipMemcpy(out + 5 * N, d_phi, N * sizeof(double), hipMemcpyDeviceToHost));
+        CHECK_HIP(hipFree(d_pi));
+    }
     hub_destroy(ctx);
     CHECK_HIP(hipFree(d_phi));
     CHECK_HIP(hipFree(d_chi));
@@ -100,7 +123,10 @@ int main(int argc, char** argv) {
     f = fopen(argv[7], "wb");
     if (!f || fwrite(out, sizeof(double), 5 * N, f) != 5 * N ||
         fwrite(&info.iters, sizeof(int32_t), 1, f) != 1 ||
-        fwrite(&info.true_rel_res, sizeof(double), 1, f) != 1) {
+        fwrite(&info.true_rel_res, sizeof(double), 1, f) != 1 ||
+        (traj && (fwrite(&tinfo.accepted, sizeof(int32_t), 1, f) != 1 ||
+                  fwrite(&tinfo.dH, sizeof(double), 1, f) != 1 ||
+                  fwrite(out + 5 * N, sizeof(double), N, f) != N))) {
         fprintf(stderr, "cannot write %s\n", argv[7]);
         return 1;
     }
@@ -108,5 +134,6 @@ int main(int argc, char** argv) {
     free(phi);
     free(chi);
     free(out);
+    free(pi0);
     return 0;
 }

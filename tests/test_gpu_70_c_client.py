@@ -63,3 +63,32 @@ def test_c_client_small_weak_field(tmp_path):
     rr = np.linalg.norm(chi[0] - op.apply_A(phi, x[None])[0]) / np.linalg.norm(chi[0])
     assert rr <= 1.01e-10, rr
     assert_close_elementwise(g, O.force(op, phi, x[None]), 1e-12, "force")
+
+
+def test_c_client_runs_an_hmc_trajectory(tmp_path):
+    """hub_trajectory called from plain C: one leapfrog trajectory with rho = chi, against
+    the oracle trajectory from the same numbers (decision, dH and the resulting field)."""
+    from oracle import hmc as OH
+    w = TINY
+    phi = draw_weak_field(w, seed=33)[0]
+    _, rho = draw_inputs(w, seed=34)
+    pi = np.random.default_rng(35).normal(size=(w.Nt, w.V))
+    u = 0.5
+    src, dst = tmp_path / "in.bin", tmp_path / "out.bin"
+    with open(src, "wb") as f:
+        f.write(np.ascontiguousarray(phi).tobytes())
+        f.write(np.ascontiguousarray(rho[0]).tobytes())
+        f.write(np.ascontiguousarray(pi).tobytes())
+    r = subprocess.run([DRIVER, str(w.L), str(w.Nt), repr(w.beta), repr(w.kappa), "0", str(src), str(dst),
+                        repr(w.U), "0.05", "8", repr(u)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    raw = open(dst, "rb").read()
+    off = 5 * w.N * 8 + 4 + 8
+    accepted = int(np.frombuffer(raw[off: off + 4], dtype=np.int32)[0])
+    dH = float(np.frombuffer(raw[off + 4: off + 12], dtype=np.float64)[0])
+    phi_after = np.frombuffer(raw[off + 12:], dtype=np.float64).reshape(w.Nt, w.V)
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+    _, _, dH_ref, acc_ref, out_ref = OH.trajectory(op, w.U, phi, pi, rho, u, n_md=8, eps=0.05)
+    assert bool(accepted) == acc_ref
+    assert abs(dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref)), (dH, dH_ref)
+    np.testing.assert_allclose(phi_after, out_ref, rtol=0, atol=1e-8)
