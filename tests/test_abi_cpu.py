@@ -159,3 +159,22 @@ def test_plain_c_client_compiles_and_links(tmp_path):
                     "-o", str(exe)], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 1 and "usage" in r.stderr
+
+
+def test_host_tables_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The host-side table builder (plans, roots, E(k)) built with AddressSanitizer and
+    UBSan (fatal on the first report) runs clean for every supported kind of length and
+    prints exactly what the plain build prints."""
+    src = [os.path.join(ROOT, "tests", "host", "tables_driver.cpp"), os.path.join(CSRC, "hub_tables.cpp")]
+    plain, san = tmp_path / "tables_plain", tmp_path / "tables_san"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, *src, "-o", str(plain)], check=True)
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined", "-I", CSRC, *src, "-o", str(san)], check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    for L, dk, dmu in [(1, 0.1, 0.0), (2, 0.3, 0.0), (3, 0.1, 0.2), (17, 0.05, 0.0), (51, 0.0625, -0.1),
+                       (102, 0.0625, 0.0), (19, 0.1, 0.0)]:
+        a = subprocess.run([str(plain), str(L), repr(dk), repr(dmu)], capture_output=True, text=True, check=True)
+        b = subprocess.run([str(san), str(L), repr(dk), repr(dmu)], capture_output=True, text=True, env=env)
+        assert b.returncode == 0, (L, b.stderr[-2000:])
+        assert "runtime error" not in b.stderr and "AddressSanitizer" not in b.stderr, (L, b.stderr[-2000:])
+        assert a.stdout == b.stdout, L
