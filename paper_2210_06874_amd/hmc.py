@@ -11,6 +11,7 @@ the two device-reduced energies.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import torch
@@ -37,3 +38,67 @@ def trajectory(hub, phi: torch.Tensor, U: float, pi0: torch.Tensor, rho: torch.T
     info = hub.trajectory(phi, pi0, rho, u, U, n_md, eps, integrator=integrator, tol=tol, prec=prec,
                           max_iter=max_iter)
     return Trajectory(bool(info.accepted), info.dH, info.H0, info.H1, info.cg_iters, info.n_forces)
+
+
+# ----------------------------------------------------------------------------- Markov chains
+@dataclass
+class ChainState:
+    k: int                 # trajectories done
+    accepted: int          # of which accepted
+    dH: list               # dH of every trajectory done in this run
+
+
+def draw_trajectory_randoms(rng, Nt: int, V: int, nrhs: int = 1):
+    """The random numbers of one trajectory, on the host, in this order: momenta
+    pi ~ e^{-pi^2/2} (float64 [Nt, V]), heat-bath vectors rho ~ e^{-rho^dag rho}
+    (complex128 [nrhs, Nt, V]: real parts, then imaginary parts) and the uniform u."""
+    import numpy as np
+    pi = rng.normal(0.0, 1.0, size=(Nt, V))
+    s = math.sqrt(0.5)
+    rho = rng.normal(0.0, s, size=(nrhs, Nt, V)) + 1j * rng.normal(0.0, s, size=(nrhs, Nt, V))
+    return pi, rho, float(rng.random())
+
+
+def save_checkpoint(path: str, phi, rng, state: ChainState) -> None:
+    """Field, generator state and counters in one .npz (no pickled objects), written to a
+    temporary file and renamed, so an interrupted write never replaces a good checkpoint."""
+    import json
+    import os
+    import numpy as np
+    phi_h = phi.detach().cpu().numpy() if isinstance(phi, torch.Tensor) else np.asarray(phi)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, phi=phi_h, k=np.int64(state.k), accepted=np.int64(state.accepted),
+             rng=np.array(json.dumps(rng.bit_generator.state)))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path: str):
+    """(phi as float64 [Nt, V] numpy, generator, ChainState) from save_checkpoint's file."""
+    import json
+    import numpy as np
+    with np.load(path, allow_pickle=False) as z:
+        st = json.loads(str(z["rng"]))
+        bg = getattr(np.random, st["bit_generator"])()
+        bg.state = st
+        return np.array(z["phi"]), np.random.Generator(bg), ChainState(int(z["k"]), int(z["accepted"]), [])
+
+
+def run_chain(hub, phi: torch.Tensor, U: float, n_traj: int, n_md: int, eps: float, rng, nrhs: int = 1,
+              state: ChainState | None = None, checkpoint: str | None = None, every: int = 10,
+              **traj_kw) -> ChainState:
+    """Run trajectories until `n_traj` are done in total (counting those in `state`), drawing
+    each trajectory's random numbers from the numpy generator `rng`.  `phi` (device) is the
+    chain's field, updated in place.  With `checkpoint`, the field, the generator and the
+    counters are saved every `every` trajectories and at the end; a chain resumed from
+    load_checkpoint continues exactly as if it had not stopped."""
+    state = ChainState(0, 0, []) if state is None else state
+    while state.k < n_traj:
+        pi, rho, u = draw_trajectory_randoms(rng, hub.Nt, hub.V, nrhs)
+        tr = trajectory(hub, phi, U, torch.from_numpy(pi).to(phi.device), torch.from_numpy(rho).to(phi.device),
+                        u, n_md, eps, **traj_kw)
+        state.k += 1
+        state.accepted += int(tr.accepted)
+        state.dH.append(tr.dH)
+        if checkpoint and (state.k % every == 0 or state.k == n_traj):
+            save_checkpoint(checkpoint, phi, rng, state)
+    return state

@@ -150,3 +150,27 @@ def test_failed_trajectory_restores_the_field():
     info = hub.trajectory(P, to_dev(pi), to_dev(rho), 0.999, w.U, n_md=4, eps=0.2, tol=1e-12, prec="fp64")
     assert info.accepted == 0 and abs(info.dH - dH_ref) < 1e-7 * dH_ref, (info.dH, dH_ref)
     assert np.array_equal(to_np(P), phi0)
+
+
+def test_chain_resumed_from_a_checkpoint_continues_exactly(tmp_path):
+    """Six trajectories in one run, and three, a checkpoint, a resume from the file into a new
+    field, and three more: the same field bit for bit and the same dH sequence."""
+    from paper_2210_06874_amd import Hubbard, hmc
+    w = TINY
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa)
+    phi0 = draw_weak_field(w)[0]
+    kw = dict(tol=1e-12, prec="mixed")
+    A = to_dev(phi0)
+    a = hmc.run_chain(hub, A, w.U, 6, 5, 0.08, np.random.default_rng(77), **kw)
+    B = to_dev(phi0)
+    path = str(tmp_path / "chain.npz")
+    b1 = hmc.run_chain(hub, B, w.U, 3, 5, 0.08, np.random.default_rng(77), checkpoint=path, every=3, **kw)
+    del B
+    phi_c, rng_c, st = hmc.load_checkpoint(path)
+    assert st.k == 3
+    C = to_dev(phi_c)
+    b2 = hmc.run_chain(hub, C, w.U, 6, 5, 0.08, rng_c, state=st, **kw)
+    assert b2.k == 6
+    assert torch.equal(A, C)
+    assert a.dH == b1.dH + b2.dH
+    assert a.accepted == b2.accepted
