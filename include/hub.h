@@ -107,6 +107,11 @@ typedef struct {
                                right-hand side, this many consecutive reliable updates found the
                                iterated residual below tol but no 1 % gain on the best true
                                residual (the attainable-accuracy floor); 0: off               */
+    double* history_host;   /* optional (NULL: off), HOST memory [nrhs][history_len]: the true
+                               relative residual ||chi - A x|| / ||chi|| after each reliable update
+                               of right-hand side r at history_host[r * history_len + j], j = 0, 1, ..;
+                               entries past hub_cg_info.reliable_updates (or history_len) untouched */
+    int32_t history_len;    /* entries per right-hand side in history_host, >= 0                    */
 } hub_cg_opts;
 
 typedef struct {
@@ -194,8 +199,8 @@ typedef struct {
     int32_t n_md;           /* steps per trajectory, >= 1                                           */
     int32_t integrator;     /* hub_integrator: leapfrog (n_md + 1 forces) or the second-order
                                minimum-norm scheme of Omelyan, Mryglod and Folk (2 n_md + 1)         */
-    hub_cg_opts cg;         /* every solve of the trajectory; use_x0 is ignored (the first solve
-                               starts from 0, the others from the previous solution)               */
+    hub_cg_opts cg;         /* every solve of the trajectory; use_x0 and the history are ignored
+                               (the first solve starts from 0, the others from the previous one)   */
 } hub_traj_opts;
 
 typedef struct {

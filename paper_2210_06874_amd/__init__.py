@@ -37,6 +37,7 @@ class CgResult:
     reliable_updates: list
     true_rel_res: list
     recursive_rel_res: list
+    history: list | None = None     # per rhs: true relative residual after each reliable update
 
     @property
     def converged(self) -> bool:
@@ -142,7 +143,7 @@ class Hubbard:
     # ------------------------------------------------------------------ solver, action, force
     def cg_solve(self, phi, chi, tol: float = 1e-10, max_iter: int = 100000, prec: str = "fp64",
                  reliable_every: int = 50, x0=None, raise_on_error: bool = True,
-                 stall_updates: int = 0) -> CgResult:
+                 stall_updates: int = 0, history: bool = False) -> CgResult:
         """x = (M M^dag)^{-1} chi by conjugate gradients (true FP64 residual <= tol).
 
         stall_updates > 0 ends a solve stuck at its attainable accuracy early (HUB_ERR_NOCONV):
@@ -156,8 +157,13 @@ class Hubbard:
         else:
             x, _ = self._vec(x0.clone(), name="x0")
             use_x0 = 1
+        hist = None
+        if history:
+            import numpy as np
+            hist = np.full((nrhs, int(max_iter) // max(1, int(reliable_every)) + 2), np.nan)
         opts = _lib.HubCgOpts(float(tol), int(max_iter), int(reliable_every), _PREC[prec], use_x0,
-                              int(stall_updates))
+                              int(stall_updates), None if hist is None else hist.ctypes.data,
+                              0 if hist is None else hist.shape[1])
         info = (_lib.HubCgInfo * nrhs)()
         with torch.cuda.device(self.device):
             st = self.lib.hub_cg_solve(self._h, self._p(phi), self._p(chi3), self._p(x), nrhs,
@@ -167,6 +173,8 @@ class Hubbard:
         res = CgResult(x if chi.dim() == 3 else x[0], st,
                        [i.iters for i in info], [i.reliable_updates for i in info],
                        [i.true_rel_res for i in info], [i.recursive_rel_res for i in info])
+        if hist is not None:
+            res.history = [hist[r, :min(info[r].reliable_updates, hist.shape[1])].copy() for r in range(nrhs)]
         return res
 
     def force(self, phi, x, out=None):

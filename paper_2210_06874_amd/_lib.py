@@ -25,7 +25,8 @@ class HubParams(ctypes.Structure):
 class HubCgOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("reliable_every", ctypes.c_int32), ("prec", ctypes.c_int32), ("use_x0", ctypes.c_int32),
-                ("stall_updates", ctypes.c_int32)]
+                ("stall_updates", ctypes.c_int32), ("history_host", ctypes.c_void_p),
+                ("history_len", ctypes.c_int32)]
 
 
 class HubCgInfo(ctypes.Structure):

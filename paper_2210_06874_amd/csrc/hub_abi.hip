@@ -479,7 +479,7 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     const long long lookahead = std::min<long long>(4, every);
     // stagnation watch: per rhs, the best true ||r||^2 seen and the consecutive stalled updates
     std::vector<double> best(nrhs, HUGE_VAL);
-    std::vector<int> seen(nrhs, 0), stalled(nrhs, 0);
+    std::vector<int> seen(nrhs, 0), stalled(nrhs, 0), logged(nrhs, 0);
     for (;;) {
         HIP_OR_FAIL(hipMemcpyAsync(c->scal_host, sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, st));
         HIP_OR_FAIL(hipEventRecord(c->cg_event, st));
@@ -494,6 +494,12 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
             const CgScalars& h = c->scal_host[r];
             all_done &= h.done != 0;
             bad |= h.nonfinite != 0;
+            if (o.history_host && h.reliable > logged[r] && h.reliable <= o.history_len) {
+                // each host check follows exactly one reliable update
+                o.history_host[(size_t)r * o.history_len + h.reliable - 1] =
+                    std::sqrt(h.true_rr / (h.chichi > 0 ? h.chichi : 1.0));
+                logged[r] = h.reliable;
+            }
             if (h.done) continue;
             if (h.reliable > seen[r]) {
                 // a stalled update: the iterated residual had met tol, the true one made no
@@ -691,6 +697,8 @@ hub_status hub_cg_solve(hub_ctx* c, const double* phi, const void* chi, void* x,
     if (opts->prec != HUB_PREC_FP64 && opts->prec != HUB_PREC_MIXED) return fail(HUB_ERR_ARG, "bad prec");
     if (opts->use_x0 != 0 && opts->use_x0 != 1) return fail(HUB_ERR_ARG, "use_x0 must be 0 or 1");
     if (opts->stall_updates < 0) return fail(HUB_ERR_ARG, "stall_updates must be >= 0");
+    if (opts->history_len < 0 || (opts->history_len > 0 && !opts->history_host))
+        return fail(HUB_ERR_ARG, "history_len must be >= 0, with history_host set when > 0");
     s = ensure_cg_workspace(c);
     if (s != HUB_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -804,6 +812,8 @@ hub_status hub_trajectory(hub_ctx* c, double* phi, const double* pi0, const void
     hub_status s = hub_apply_M(c, phi, rho, chi, nrhs, stream);     // heat bath chi = M rho
     if (s != HUB_OK) return finish(s);
     hub_cg_opts cg = o->cg;
+    cg.history_host = nullptr;        // one history per solve would overwrite itself
+    cg.history_len = 0;
     std::vector<hub_cg_info> ci(nrhs);
     int iters = 0, n_forces = 0;
     auto solve = [&](int use_x0) -> hub_status {

@@ -9,9 +9,10 @@ int main(void) {
            offsetof(hub_params, Nt), offsetof(hub_params, beta), offsetof(hub_params, kappa),
            offsetof(hub_params, nrhs_max), offsetof(hub_params, path), offsetof(hub_params, mu),
            offsetof(hub_params, form));
-    printf("hub_cg_opts %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hub_cg_opts), offsetof(hub_cg_opts, tol),
+    printf("hub_cg_opts %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hub_cg_opts), offsetof(hub_cg_opts, tol),
            offsetof(hub_cg_opts, max_iter), offsetof(hub_cg_opts, reliable_every), offsetof(hub_cg_opts, prec),
-           offsetof(hub_cg_opts, use_x0), offsetof(hub_cg_opts, stall_updates));
+           offsetof(hub_cg_opts, use_x0), offsetof(hub_cg_opts, stall_updates), offsetof(hub_cg_opts, history_host),
+           offsetof(hub_cg_opts, history_len));
     printf("hub_cg_info %zu %zu %zu %zu %zu\n", sizeof(hub_cg_info), offsetof(hub_cg_info, iters),
            offsetof(hub_cg_info, reliable_updates), offsetof(hub_cg_info, true_rel_res),
            offsetof(hub_cg_info, recursive_rel_res));

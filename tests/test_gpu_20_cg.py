@@ -234,3 +234,27 @@ def test_cg_two_rhs_at_the_precision_workload():
         x1 = to_np(one.x)[0]
         assert np.linalg.norm(x2[k] - x1) <= 1e-5 * np.linalg.norm(x1)
         assert abs(res.iters[k] - one.iters[0]) <= 0.05 * one.iters[0]
+
+
+def test_cg_residual_history():
+    """history=True: one true relative residual per reliable update and right-hand side, the
+    last one the solver's reported residual; a history length without a buffer is refused."""
+    import ctypes
+    from paper_2210_06874_amd import _lib as L
+    w = SMALL.with_(nrhs=2)
+    phi = draw_inputs(w)[0]
+    rho = draw_complex(w, nrhs=2, seed=12)
+    chi = oracle_op(w).apply_M(phi, rho)
+    hub = _hub(w, nrhs=2)
+    res = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-11, prec="mixed", max_iter=40000, history=True)
+    assert res.converged
+    for r in range(2):
+        h = res.history[r]
+        assert len(h) == res.reliable_updates[r] >= 2 and np.all(np.isfinite(h))
+        assert h[-1] == res.true_rel_res[r] and h[-1] <= 1e-11 < h[0]
+    opts = L.HubCgOpts(1e-10, 100, 50, 0, 0, 0, None, 4)
+    P, C = to_dev(phi), to_dev(chi)
+    X = torch.empty_like(C)
+    st = hub.lib.hub_cg_solve(hub._h, ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(C.data_ptr()),
+                              ctypes.c_void_p(X.data_ptr()), 2, ctypes.byref(opts), None, None)
+    assert st == L.HUB_ERR_ARG
