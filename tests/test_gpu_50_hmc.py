@@ -174,3 +174,23 @@ def test_chain_resumed_from_a_checkpoint_continues_exactly(tmp_path):
     assert torch.equal(A, C)
     assert a.dH == b1.dH + b2.dH
     assert a.accepted == b2.accepted
+
+
+@pytest.mark.parametrize("mu", [0.4, -0.25])
+def test_trajectory_with_chemical_potential_matches_oracle(mu):
+    """Away from half filling (Sec. 3) the pseudofermion Hamiltonian samples |det M[phi, mu]|^2;
+    the device trajectory follows the oracle's with the same numbers."""
+    from paper_2210_06874_amd import Hubbard, hmc
+    w = TINY
+    print(f"[case] hmc trajectory mu={mu} {w.name}", flush=True)
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa, mu=mu)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, mu=mu)
+    phi0 = draw_weak_field(w)[0]
+    for k, (pi, rho, u) in enumerate(draw_hmc_randoms(w, 2, seed=13)):
+        _, _, dH_ref, acc_ref, out_ref = OH.trajectory(op, w.U, phi0, pi, rho, u, n_md=6, eps=0.05)
+        P = to_dev(phi0)
+        tr = hmc.trajectory(hub, P, w.U, to_dev(pi), to_dev(rho), u, n_md=6, eps=0.05, tol=1e-12, prec="mixed")
+        assert abs(tr.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref)), (k, tr.dH, dH_ref)
+        assert tr.accepted == acc_ref
+        np.testing.assert_allclose(to_np(P), out_ref, atol=1e-8)
+        phi0 = out_ref
