@@ -205,7 +205,7 @@ typedef struct {
 
 typedef struct {
     int32_t accepted;       /* 1: phi holds the end of the trajectory; 0: phi was restored          */
-    int32_t n_forces;       /* force evaluations (= CG solves after the first)                      */
+    int32_t n_forces;       /* force evaluations, one per CG solve (the first also serves H0)      */
     int32_t cg_iters;       /* CG iterations over all solves, largest right-hand side count each    */
     double H0, H1, dH;      /* Hamiltonian at the start and end (FP64), dH = H1 - H0                */
 } hub_traj_info;
