@@ -194,3 +194,21 @@ def test_trajectory_with_chemical_potential_matches_oracle(mu):
         assert tr.accepted == acc_ref
         np.testing.assert_allclose(to_np(P), out_ref, atol=1e-8)
         phi0 = out_ref
+
+
+def test_device_chain_satisfies_the_equilibrium_identity():
+    """<e^{-dH}> = 1 over a 1,000-trajectory device chain (hmc.run_chain through hub_trajectory,
+    its own random numbers) on a 2 x 2 torus, N_t = 4, beta = 1, U = 2, after 100 trajectories
+    of burn-in: within 5 batch-mean standard errors."""
+    import math
+    from paper_2210_06874_amd import Hubbard, hmc
+    from workloads import Lattice
+    w = Lattice("L2_Nt4", 2, 4, 1.0, 2.0)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa)
+    P = torch.zeros((w.Nt, w.V), dtype=torch.float64, device=dev())
+    st = hmc.run_chain(hub, P, w.U, 1100, 20, 0.05, np.random.default_rng(2024), tol=1e-12, prec="fp64")
+    ex = np.array([math.exp(-d) if d > -700 else math.inf for d in st.dH[100:]])
+    b = ex[: len(ex) // 20 * 20].reshape(20, -1).mean(axis=1)
+    m, se = ex.mean(), b.std() / math.sqrt(20)
+    print(f"    <exp(-dH)> = {m:.4f} +- {se:.4f}, acceptance {st.accepted / st.k:.2f}", flush=True)
+    assert se < 0.01 and abs(m - 1.0) < 5 * se, (m, se)
