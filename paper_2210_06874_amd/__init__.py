@@ -71,9 +71,16 @@ class Hubbard:
         self.lds_bytes = lds.value
 
     def close(self):
+        """Release the context's device memory now (also done when the object is collected)."""
         if getattr(self, "_h", None):
             self.lib.hub_destroy(self._h)
             self._h = None
+
+    def __enter__(self) -> "Hubbard":
+        return self
+
+    def __exit__(self, *exc) -> None:
+        self.close()
 
     def __del__(self):
         try:

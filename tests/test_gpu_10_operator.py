@@ -380,3 +380,18 @@ def test_phase_accuracy_over_the_angle_range(prec):
         tol = np.where(np.abs(ref_phi) < 6000.0, 2.0 * np.abs(ref_phi) * 2.0 ** -24, 0.0) + 1e-6
     bad = np.argwhere(err > tol)
     assert bad.size == 0, [(float(ref_phi[tuple(i)]), float(err[tuple(i)]), float(tol[tuple(i)])) for i in bad[:5]]
+
+
+def test_context_manager_releases_the_context():
+    """`with Hubbard(...) as hub:` destroys the context on exit; a later call is refused
+    (HubError for a NULL context), never run on freed memory."""
+    from paper_2210_06874_amd import Hubbard, HubError
+    w = TINY
+    phi, v = draw_inputs(w)
+    P, V = to_dev(phi), to_dev(v)
+    with Hubbard(w.L, w.Nt, w.beta, w.kappa) as hub:
+        ref = hub.apply_M(P, V)
+    assert hub._h is None
+    with pytest.raises(HubError):
+        hub.apply_M(P, V)
+    assert torch.isfinite(ref.real).all()
