@@ -47,28 +47,50 @@ def test_hopping_bipartite_degree_three(L):
     np.testing.assert_array_equal(sig[:, None] * K * sig[None, :], -K)
 
 
-def test_hopping_brute_force_L3():
-    """Brute force: enumerate honeycomb coordinates and link sites at unit distance."""
+def _figure_geometry():
+    """tests/golden/honeycomb_figure_geometry.txt: the Sec. 1 figure's own coordinates."""
+    import os
+    vals, bonds = {}, []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "honeycomb_figure_geometry.txt")) as f:
+        for line in f:
+            parts = line.split()
+            if not parts or parts[0].startswith("#"):
+                continue
+            if parts[0] == "bond":
+                bonds.append(np.array([float(parts[1]), float(parts[2])]))
+            else:
+                vals[parts[0]] = float(parts[1])
+    return vals, bonds
+
+
+def test_hopping_brute_force_from_the_figure_L3():
+    """Brute force from the paper's drawing (Sec. 1 figure, golden fixture): place A sites on the
+    figure's triangular lattice and B sites along its horizontal bond, link sites at unit
+    distance on the L = 3 torus, and compare with the oracle's K.  The figure's other two
+    bond vectors are the oracle's B(n - e2) and B(n - e1) neighbours."""
     L = 3
-    a1 = np.array([1.5, math.sqrt(3) / 2])
-    a2 = np.array([1.5, -math.sqrt(3) / 2])
-    off = {0: np.zeros(2), 1: np.array([1.0, 0.0])}        # A at cell origin, B shifted
+    g, bonds = _figure_geometry()
+    cs, rs, sh = g["column_spacing"], g["row_spacing"], g["odd_column_shift"]
+    a1 = np.array([cs, sh])             # A(column 1, row 0) - A(0, 0)
+    a2 = np.array([cs, sh - rs])        # A(column 1, row -1) - A(0, 0)
+    b0 = bonds[0]                       # B(n) = A(n) + the horizontal bond
+    assert len(bonds) == 3 and all(abs(np.linalg.norm(b) - 1.0) < 1e-3 for b in bonds)
+    np.testing.assert_allclose(bonds[1], -a2 + b0, atol=2e-3)     # B(n - e2)
+    np.testing.assert_allclose(bonds[2], -a1 + b0, atol=2e-3)     # B(n - e1)
     pos = {}
     for s in (0, 1):
         for n1 in range(L):
             for n2 in range(L):
-                pos[O.site_index(L, s, n1, n2)] = n1 * a1 + n2 * a2 + off[s]
-    # torus: distance minimised over periodic images
+                pos[O.site_index(L, s, n1, n2)] = n1 * a1 + n2 * a2 + (b0 if s else 0.0)
+    # torus: distance minimised over periodic images; the next-nearest distance is sqrt(3)
     V = 2 * L * L
     K = np.zeros((V, V))
     for x in range(V):
         for y in range(V):
             d = min(np.linalg.norm(pos[x] - pos[y] + i * L * a1 + j * L * a2)
                     for i in (-1, 0, 1) for j in (-1, 0, 1))
-            if abs(d - 1.0) < 1e-9:
+            if abs(d - 1.0) < 0.02:
                 K[x, y] = 1.0
-    # B(n) sits at +(1,0) from A(n); the other two neighbours are B(n - e1), B(n - e2)
-    # under the lattice vectors a1 = (3/2, sqrt3/2), a2 = (3/2, -sqrt3/2).
     np.testing.assert_array_equal(K, O.hopping_matrix(L))
 
 
