@@ -115,13 +115,6 @@ def test_free_log_det_closed_form(L, Nt, beta):
     assert abs(sign - 1) < 1e-12
 
 
-def test_free_log_det_tiny_workload_value():
-    """The tiny workload's free log det, a fixed number of the closed form."""
-    op = _op(TINY)
-    _, ld = np.linalg.slogdet(op.dense_M(np.zeros((TINY.Nt, TINY.V))))
-    assert abs(ld - 29.932004444908) < 1e-10
-
-
 @pytest.mark.parametrize("seed", [0, 1])
 def test_uniform_phase_log_det(seed):
     """phi_{t,x} = c_t (slice-uniform): det M = prod_{k,+-}(1 + e^{i sum c} e^{+-beta kappa |f|})."""
