@@ -395,3 +395,34 @@ def test_context_manager_releases_the_context():
     with pytest.raises(HubError):
         hub.apply_M(P, V)
     assert torch.isfinite(ref.real).all()
+
+
+@pytest.mark.parametrize("L,Nt,nrhs", [(51, 255, 1), (51, 127, 2), (51, 60, 4), (51, 1, 1), (51, 3, 3),
+                                       (102, 5, 3), (102, 1, 2)])
+def test_production_lengths_at_odd_shapes(L, Nt, nrhs):
+    """The compile-time L = 51 and L = 102 kernels on both sides of the two-workgroup switch
+    (fewer than 256 slices), with several right-hand sides, a single slice and odd N_t: M, M^dag,
+    FP32 M and the force on sampled slices against the oracle's Krylov route."""
+    from paper_2210_06874_amd import Hubbard
+    print(f"[case] production length L={L} Nt={Nt} nrhs={nrhs}", flush=True)
+    w = Lattice(f"L{L}_Nt{Nt}", L, Nt, 0.0625 * Nt, 3.9, nrhs=nrhs)
+    phi, v = draw_inputs(w, seed=L + Nt, nrhs=nrhs)
+    op = oracle_op(w, mode="expm")
+    hub = Hubbard(L, Nt, w.beta, w.kappa, nrhs_max=nrhs)
+    P, V = to_dev(phi), to_dev(v)
+    M64, D64 = to_np(hub.apply_M(P, V)), to_np(hub.apply_Mdag(P, V))
+    p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
+    M32 = to_np(hub.apply_M_c64(to_dev(p32), to_dev(v32)))
+    g = to_np(hub.force(P, V))
+    p64, v64 = p32.astype(np.float64), v32.astype(np.complex128)
+    for t in sorted({0, Nt // 2, Nt - 1}):
+        tp, tn = (t - 1) % Nt, (t + 1) % Nt
+        Bt, Btn = (-1.0 if t == 0 else 1.0), (-1.0 if tn == 0 else 1.0)
+        wv = op.apply_E(v[:, tn])
+        assert_close_elementwise(M64[:, t], v[:, t] - Bt * op.apply_E(np.exp(1j * phi[tp])[None] * v[:, tp]),
+                                 RTOL64, f"M slice {t}")
+        assert_close_elementwise(D64[:, t], v[:, t] - Btn * np.exp(-1j * phi[t])[None] * wv, RTOL64, f"Mdag slice {t}")
+        assert_close_elementwise(M32[:, t], v64[:, t] - Bt * op.apply_E(np.exp(1j * p64[tp])[None] * v64[:, tp]),
+                                 RTOL32, f"M32 slice {t}")
+        gref = (-2.0 * Btn * (np.exp(1j * phi[t])[None] * v[:, t] * np.conj(wv)).imag).sum(axis=0)
+        assert_close_elementwise(g[t], gref, 1e-11, f"force slice {t}")
