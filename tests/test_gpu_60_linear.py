@@ -274,3 +274,23 @@ def test_apply_maximum_lattice():
     op = _op(w)
     assert_close_elementwise(to_np(hub.apply_M(to_dev(phi), to_dev(v))), op.apply_M(phi, v), RTOL64, "M")
     assert_close_elementwise(to_np(hub.apply_Mdag(to_dev(phi), to_dev(v))), op.apply_Mdag(phi, v), RTOL64, "Mdag")
+
+
+@pytest.mark.parametrize("L,Nt,nrhs", [(51, 1, 1), (51, 3, 4), (51, 255, 1), (51, 1024, 1), (102, 5, 3), (102, 1, 2)])
+def test_stencil_chunking_at_odd_shapes(L, Nt, nrhs):
+    """The chunk count per slice depends on N_t and nrhs (at least 256 workgroups, at most
+    1,024 reduction slots): M, M^dag, FP32 M and the force at shapes that give one chunk, many
+    chunks and a single slice, against the oracle."""
+    from paper_2210_06874_amd import Hubbard
+    print(f"[case] stencil chunking L={L} Nt={Nt} nrhs={nrhs}", flush=True)
+    w = Lattice(f"L{L}_Nt{Nt}", L, Nt, 0.0625 * Nt, 3.9, nrhs=nrhs)
+    phi, v = draw_inputs(w, seed=L + 3 * Nt, nrhs=nrhs)
+    op = _op(w)
+    hub = Hubbard(L, Nt, w.beta, w.kappa, nrhs_max=nrhs, form="linear")
+    P, V = to_dev(phi), to_dev(v)
+    assert_close_elementwise(to_np(hub.apply_M(P, V)), op.apply_M(phi, v), 1e-13, "M")
+    assert_close_elementwise(to_np(hub.apply_Mdag(P, V)), op.apply_Mdag(phi, v), 1e-13, "Mdag")
+    p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
+    assert_close_elementwise(to_np(hub.apply_M_c64(to_dev(p32), to_dev(v32))),
+                             op.apply_M(p32.astype(np.float64), v32.astype(np.complex128)), 2e-6, "M32")
+    assert_close_elementwise(to_np(hub.force(P, V)), O.force_linear(op, phi, v), 1e-12, "force")
