@@ -23,6 +23,7 @@ struct CgScalars {
     double true_rr;   // ||chi - A x_hi||^2 at the last reliable update
     double tol2;      // tol^2 * ||chi||^2
     double rec_rr;    // iterated ||r||^2 just before the last reliable update
+    double rr_last;   // ||r_i||^2 that the last iteration which did work started from
     int32_t active;   // unused (kept for layout)
     int32_t done;     // 1 once the true residual met tol
     int32_t iters;

@@ -408,10 +408,16 @@ struct FinResidual {             // after an FP64 residual recomputation (CG rel
         if (sc[r].done) return;                  // uniform: read before any thread writes
         double* cur = rr_cur + (long long)r * slots;
         double* prev = rr_prev + (long long)r * slots;
-        const double* const p[2] = {cur, prev};
-        double sum[2];
-        sum_partials_k<2>(p, slots, lds, sum);
-        const double rec = sum[0], old = sum[1];
+        const double* const pc[1] = {cur};
+        double sum[1];
+        sum_partials_k<1>(pc, slots, lds, sum);
+        const double rec = sum[0];
+        // The recursion's beta for the next iteration is rec / ||r_i||^2 of the last iteration
+        // that did work.  That value is kept in the scalars, not taken from the partials: an
+        // idle iteration (iterated residual already below tol) carries ||r||^2 forward into
+        // both partial buffers, which would turn the ratio into 1 and revive a stale, much
+        // longer search direction at full weight.
+        const double old = sc[r].rr_last;
         const bool ok = isfinite(rr);
         if (threadIdx.x == 0) {
             sc[r].reliable += 1;
@@ -424,12 +430,13 @@ struct FinResidual {             // after an FP64 residual recomputation (CG rel
         if (!ok) return;
         // The iteration continues from the recomputed residual: alpha uses ||r_true||^2,
         // while the search direction keeps the recursion's beta = rec / old (the previous
-        // entry is rescaled so that the ratio the next kernel forms is unchanged).  Every
-        // thread has read the partials (sum_partials_k ends in a barrier) before they change.
-        const bool rescale = rec > 0.0 && isfinite(rec);
+        // entry is set so that the ratio the next kernel forms is that beta).  A zero or
+        // non-finite iterated residual restarts the recursion: beta = 0.  Every thread has
+        // read the partials (sum_partials_k ends in a barrier) before they change.
+        const double pv = (rec > 0.0 && isfinite(rec)) ? old * (rr / rec) : __builtin_huge_val();
         for (int j = threadIdx.x; j < slots; j += blockDim.x) {
             cur[j] = j == 0 ? rr : 0.0;
-            if (rescale) prev[j] = j == 0 ? old * (rr / rec) : 0.0;
+            prev[j] = j == 0 ? pv : 0.0;
         }
     }
 };
@@ -448,6 +455,7 @@ struct FinInit {                 // ||chi||^2 and the starting state of every ri
         s.rr = cc;
         s.true_rr = cc;
         s.rec_rr = cc;
+        s.rr_last = cc;
         s.nonfinite = isfinite(cc) ? 0 : 1;
         s.done = (cc == 0.0) ? 1 : 0;
         sc[r] = s;
@@ -563,7 +571,10 @@ struct CtlUpdate {
             open = 0;
             if (slot == 0 && threadIdx.x == 0) sc[rhs].nonfinite = 1;
         }
-        if (open && slot == 0 && threadIdx.x == 0) sc[rhs].iters += 1;
+        if (open && slot == 0 && threadIdx.x == 0) {
+            sc[rhs].iters += 1;
+            sc[rhs].rr_last = a;
+        }
         return {open, alpha, beta};
     }
     __device__ void end(double acc, int rhs, int slot, const Scal& s, double* lds) const {

@@ -4,7 +4,7 @@ import pytest
 import torch
 
 import oracle as O
-from workloads import TINY, SMALL, DIFF_SUB, PREC, STRESS, Lattice, draw_inputs, draw_complex
+from workloads import TINY, SMALL, DIFF_SUB, PREC, STRESS, Lattice, draw_inputs, draw_complex, draw_phi
 from gpu_common import dev, to_dev, to_np, oracle_op
 import closed_forms as CF
 
@@ -258,3 +258,31 @@ def test_cg_residual_history():
     st = hub.lib.hub_cg_solve(hub._h, ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(C.data_ptr()),
                               ctypes.c_void_p(X.data_ptr()), 2, ctypes.byref(opts), None, None)
     assert st == L.HUB_ERR_ARG
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed", range(8))
+def test_cg_continues_the_recursion_after_an_idle_stretch(prec, seed):
+    """A system of 12 unknowns (L = 1, Nt = 6) whose iterated residual plunges below tol in one
+    step, long before the true FP32-limited one does: the right-hand side idles until the
+    reliable update and then resumes.  The resumed direction must take the recursion's beta
+    from the last iteration that did work; a beta formed from the idle iterations' carried
+    partials (= 1) revives the stale direction at full weight, which wanders for thousands of
+    iterations and can overflow FP32 (reported as a breakdown)."""
+    from paper_2210_06874_amd import Hubbard
+    w = Lattice("L1_Nt6", 1, 6, 4.87, 3.0, kappa=0.95, nrhs=3)
+    print(f"[case] cg idle stretch {prec} seed {seed}", flush=True)
+    rng = np.random.default_rng(seed)
+    phi = draw_phi(w, rng=rng)
+    v = draw_complex(w, nrhs=3, rng=rng)
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+    chi = op.apply_M(phi, v)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, nrhs_max=3)
+    res = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-10, prec=prec, max_iter=5000, raise_on_error=False)
+    assert res.status == 0, (res.status, res.iters)
+    x = to_np(res.x)
+    r = chi - op.apply_A(phi, x)
+    for k in range(3):
+        assert np.linalg.norm(r[k]) <= 2e-10 * np.linalg.norm(chi[k]), k
+    # the fixed recursion needs 27-60 iterations here; the stale direction took 150 to 3000+
+    assert max(res.iters) <= 100, res.iters
