@@ -150,9 +150,9 @@ hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, vo
  * "hamiltonian": the pseudofermion term needs (M M^dag)^{-1} chi).  Conjugate
  * gradients from x0 = 0 (or x on entry when opts->use_x0), all reductions in FP64.
  * With opts->prec == HUB_PREC_MIXED the iterations run in FP32 and every
- * reliable_every iterations (or as soon as the iterated residual meets tol) the
- * FP64 solution is updated and the FP64 residual recomputed.  Convergence is
- * always judged on the true FP64 residual.
+ * reliable_every iterations the FP64 solution is updated and the FP64 residual
+ * recomputed (in both precisions; a right-hand side whose iterated residual meets tol
+ * earlier idles until then).  Convergence is always judged on the true FP64 residual.
  * chi, x: complex128 [nrhs][Nt][V]; x may overlap neither chi nor phi.  info_host: nrhs entries
  * in HOST memory (may be NULL).  Returns HUB_ERR_NOCONV (x = last FP64 iterate,
  * info filled) at max_iter or on stagnation (opts->stall_updates), or
