@@ -368,11 +368,15 @@ def main() -> int:
         for prec in ("mixed", "fp64"):
             torch.cuda.synchronize()
             tp = time.perf_counter()
-            r = hub.cg_solve(Pl, Cl, tol=1e-10, prec=prec, max_iter=args.literal_probe, raise_on_error=False)
+            r = hub.cg_solve(Pl, Cl, tol=1e-10, prec=prec, max_iter=args.literal_probe, raise_on_error=False,
+                             history=True)
             torch.cuda.synchronize()
             el = time.perf_counter() - tp
+            # true relative residual after each reliable update (every 50 iterations): the
+            # non-convergence as it unfolds, not only its end point
             out[prec] = {"iters": r.iters[0], "true_rel_res": r.true_rel_res[0],
-                         "us_per_iter": el / max(1, r.iters[0]) * 1e6, "converged": r.converged}
+                         "us_per_iter": el / max(1, r.iters[0]) * 1e6, "converged": r.converged,
+                         "residual_history_every_50": [float(f"{h:.3g}") for h in r.history[0]]}
         probe = out
 
     line = {
