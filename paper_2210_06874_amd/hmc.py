@@ -45,7 +45,8 @@ def trajectory(hub, phi: torch.Tensor, U: float, pi0: torch.Tensor, rho: torch.T
 class ChainState:
     k: int                 # trajectories done
     accepted: int          # of which accepted
-    dH: list               # dH of every trajectory done in this run
+    dH: list               # dH of every trajectory done in this run (nan for a failed one)
+    failed: int = 0        # of which ended in a solver failure and counted as rejected
 
 
 def draw_trajectory_randoms(rng, Nt: int, V: int, nrhs: int = 1):
@@ -68,7 +69,7 @@ def save_checkpoint(path: str, phi, rng, state: ChainState) -> None:
     phi_h = phi.detach().cpu().numpy() if isinstance(phi, torch.Tensor) else np.asarray(phi)
     tmp = path + ".tmp.npz"
     np.savez(tmp, phi=phi_h, k=np.int64(state.k), accepted=np.int64(state.accepted),
-             rng=np.array(json.dumps(rng.bit_generator.state)))
+             failed=np.int64(state.failed), rng=np.array(json.dumps(rng.bit_generator.state)))
     os.replace(tmp, path)
 
 
@@ -80,25 +81,41 @@ def load_checkpoint(path: str):
         st = json.loads(str(z["rng"]))
         bg = getattr(np.random, st["bit_generator"])()
         bg.state = st
-        return np.array(z["phi"]), np.random.Generator(bg), ChainState(int(z["k"]), int(z["accepted"]), [])
+        failed = int(z["failed"]) if "failed" in z.files else 0
+        return np.array(z["phi"]), np.random.Generator(bg), ChainState(int(z["k"]), int(z["accepted"]), [], failed)
 
 
 def run_chain(hub, phi: torch.Tensor, U: float, n_traj: int, n_md: int, eps: float, rng, nrhs: int = 1,
               state: ChainState | None = None, checkpoint: str | None = None, every: int = 10,
-              **traj_kw) -> ChainState:
+              reject_failed: bool = False, **traj_kw) -> ChainState:
     """Run trajectories until `n_traj` are done in total (counting those in `state`), drawing
     each trajectory's random numbers from the numpy generator `rng`.  `phi` (device) is the
     chain's field, updated in place.  With `checkpoint`, the field, the generator and the
     counters are saved every `every` trajectories and at the end; a chain resumed from
-    load_checkpoint continues exactly as if it had not stopped."""
+    load_checkpoint continues exactly as if it had not stopped.
+
+    A solve that does not converge or breaks down (the molecular dynamics ran into a nearly
+    singular M, close to a zero of det M) raises, unless `reject_failed`: then the trajectory
+    counts as rejected (the library has restored phi), its dH is recorded as nan and
+    `state.failed` counts it."""
+    from ._lib import HubError, HUB_ERR_NOCONV, HUB_ERR_NONFINITE
     state = ChainState(0, 0, []) if state is None else state
     while state.k < n_traj:
         pi, rho, u = draw_trajectory_randoms(rng, hub.Nt, hub.V, nrhs)
-        tr = trajectory(hub, phi, U, torch.from_numpy(pi).to(phi.device), torch.from_numpy(rho).to(phi.device),
-                        u, n_md, eps, **traj_kw)
+        try:
+            tr = trajectory(hub, phi, U, torch.from_numpy(pi).to(phi.device),
+                            torch.from_numpy(rho).to(phi.device), u, n_md, eps, **traj_kw)
+        except HubError as e:
+            if not (reject_failed and e.status in (HUB_ERR_NOCONV, HUB_ERR_NONFINITE)):
+                raise
+            tr = None
         state.k += 1
-        state.accepted += int(tr.accepted)
-        state.dH.append(tr.dH)
+        if tr is None:
+            state.failed += 1
+            state.dH.append(math.nan)
+        else:
+            state.accepted += int(tr.accepted)
+            state.dH.append(tr.dH)
         if checkpoint and (state.k % every == 0 or state.k == n_traj):
             save_checkpoint(checkpoint, phi, rng, state)
     return state

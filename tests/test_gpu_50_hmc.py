@@ -176,6 +176,32 @@ def test_chain_resumed_from_a_checkpoint_continues_exactly(tmp_path):
     assert a.accepted == b2.accepted
 
 
+def test_chain_counts_failed_solves_as_rejections_on_request():
+    """A solve that cannot converge (max_iter = 1, forced from the host) raises out of run_chain
+    by default; with reject_failed every trajectory counts as a failed rejection, dH is nan and
+    the field is left exactly as it was."""
+    import math
+    from paper_2210_06874_amd import Hubbard, hmc
+    from paper_2210_06874_amd._lib import HubError, HUB_ERR_NOCONV
+    w = TINY
+    print(f"[case] chain with failing solves {w.name}", flush=True)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa)
+    phi0 = draw_weak_field(w)[0]
+    P = to_dev(phi0)
+    with pytest.raises(HubError) as e:
+        hmc.run_chain(hub, P, w.U, 2, 3, 0.1, np.random.default_rng(3), max_iter=1, prec="fp64")
+    assert e.value.status == HUB_ERR_NOCONV
+    assert np.array_equal(to_np(P), phi0)
+    st = hmc.run_chain(hub, P, w.U, 4, 3, 0.1, np.random.default_rng(3), max_iter=1, prec="fp64",
+                       reject_failed=True)
+    assert (st.k, st.accepted, st.failed) == (4, 0, 4)
+    assert all(math.isnan(d) for d in st.dH)
+    assert np.array_equal(to_np(P), phi0)
+    # and a healthy chain records no failure
+    ok = hmc.run_chain(hub, P, w.U, 3, 3, 0.1, np.random.default_rng(3), prec="fp64", reject_failed=True)
+    assert ok.failed == 0 and not any(math.isnan(d) for d in ok.dH)
+
+
 @pytest.mark.parametrize("mu", [0.4, -0.25])
 def test_trajectory_with_chemical_potential_matches_oracle(mu):
     """Away from half filling (Sec. 3) the pseudofermion Hamiltonian samples |det M[phi, mu]|^2;
