@@ -74,6 +74,38 @@ def test_autograd_backward_is_force():
     assert S2.item() == S.item() and torch.equal(P2.grad, P.grad)
 
 
+def test_autograd_gradient_in_chi():
+    """d S / d chi: torch's gradient of a real function of complex chi is 2 dS/dchi^* = 2 x.
+    Checked against the oracle's dense solve, and its convention against a central difference
+    of the oracle's action along a random complex direction: dS = Re sum conj(grad) d."""
+    from paper_2210_06874_amd import PseudofermionAction
+    w = TINY
+    print(f"[case] autograd chi {w.name}", flush=True)
+    phi, chi = draw_inputs(w, nrhs=2)
+    hub = _hub(w, nrhs=2)
+    C = to_dev(chi).requires_grad_(True)
+    P = to_dev(phi).requires_grad_(True)
+    S = PseudofermionAction.apply(P, C, hub, 1e-12)
+    S.backward()
+    gc = to_np(C.grad)
+    op = oracle_op(w)
+    x_ref = O.dense_solve(op, phi, chi)
+    cond = np.linalg.cond(op.dense_M(phi) @ op.dense_M(phi).conj().T)
+    assert np.linalg.norm(gc - 2 * x_ref) <= 4 * cond * 1e-12 * np.linalg.norm(2 * x_ref)
+    d = draw_complex(w, nrhs=2, seed=31)
+    h = 1e-4
+    Sp = O.action(chi + h * d, O.dense_solve(op, phi, chi + h * d))
+    Sm = O.action(chi - h * d, O.dense_solve(op, phi, chi - h * d))
+    fd = (Sp - Sm) / (2 * h)
+    assert abs(fd - float(np.real(np.vdot(gc, d)))) <= 1e-6 * abs(fd)
+    # phi's gradient is unchanged by also differentiating in chi
+    assert torch.equal(P.grad, hub.force(to_dev(phi), hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-12).x))
+    # a 2-D chi (one right-hand side) gets a 2-D gradient
+    C1 = to_dev(chi[0]).requires_grad_(True)
+    PseudofermionAction.apply(to_dev(phi), C1, _hub(w), 1e-12).backward()
+    assert C1.grad.shape == C1.shape
+
+
 def test_force_gauge_sum_rule_precision_workload():
     """sum_x g_{s-1,x} - sum_x g_{s,x} = -2 Im(chi_s^dag x_s) (P8) with x = hub's solution
     of a chi = M rho system on the weak-field L = 51 workload."""
