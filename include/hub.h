@@ -153,6 +153,10 @@ hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, vo
  * reliable_every iterations the FP64 solution is updated and the FP64 residual
  * recomputed (in both precisions; a right-hand side whose iterated residual meets tol
  * earlier idles until then).  Convergence is always judged on the true FP64 residual.
+ * Every reduction has a fixed order, so repeating a call gives bitwise the same x and info.
+ * Each right-hand side has its own scalars and schedule; solved in a batch it gives bitwise the
+ * result of solving it alone whenever both launches use the same kernel variant (at L = 51 the
+ * variant changes where nrhs * Nt crosses 256 slices).
  * chi, x: complex128 [nrhs][Nt][V]; x may overlap neither chi nor phi.  info_host: nrhs entries
  * in HOST memory (may be NULL).  Returns HUB_ERR_NOCONV (x = last FP64 iterate,
  * info filled) at max_iter or on stagnation (opts->stall_updates), or
