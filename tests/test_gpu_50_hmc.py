@@ -5,7 +5,7 @@ import torch
 
 import oracle as O
 from oracle import hmc as OH
-from workloads import TINY, SMALL, draw_weak_field, draw_hmc_randoms
+from workloads import TINY, SMALL, Lattice, draw_weak_field, draw_hmc_randoms
 from gpu_common import dev, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
@@ -48,6 +48,28 @@ def test_trajectory_matches_oracle(prec, integrator):
         tr = hmc.trajectory(hub, P, w.U, to_dev(pi), to_dev(rho), u, n_md=8, eps=0.05, tol=1e-12, prec=prec,
                             integrator=integrator)
         assert tr.n_forces == (9 if integrator == "leapfrog" else 17)
+        assert abs(tr.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref)), (tr.dH, dH_ref)
+        assert tr.accepted == acc_ref
+        np.testing.assert_allclose(to_np(P), out_ref, atol=1e-8)
+        phi0 = out_ref
+
+
+@pytest.mark.parametrize("integrator,n_md,eps", [("leapfrog", 10, 0.05), ("omelyan", 5, 0.1)])
+def test_trajectory_matches_oracle_on_a_6x6_torus(integrator, n_md, eps):
+    """Two chained trajectories on a 6 x 6 torus (72 sites), N_t = 16, with the same random numbers
+    as the oracle: the same dH, the same decision and the same field."""
+    from paper_2210_06874_amd import hmc
+    w = Lattice("L6_Nt16", 6, 16, 2.0, 2.0)
+    print(f"[case] hmc trajectory {integrator} {w.name}", flush=True)
+    phi0 = draw_weak_field(w)[0]
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+    hub = _hub(w)
+    for pi, rho, u in draw_hmc_randoms(w, 2, seed=8):
+        _, _, dH_ref, acc_ref, out_ref = OH.trajectory(op, w.U, phi0, pi, rho, u, n_md=n_md, eps=eps,
+                                                       integrator=integrator)
+        P = to_dev(phi0)
+        tr = hmc.trajectory(hub, P, w.U, to_dev(pi), to_dev(rho), u, n_md=n_md, eps=eps, tol=1e-12, prec="fp64",
+                            integrator=integrator)
         assert abs(tr.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref)), (tr.dH, dH_ref)
         assert tr.accepted == acc_ref
         np.testing.assert_allclose(to_np(P), out_ref, atol=1e-8)
