@@ -54,16 +54,18 @@ def test_trajectory_matches_oracle(prec, integrator):
         phi0 = out_ref
 
 
+@pytest.mark.parametrize("form", ["exp", "linear"])
 @pytest.mark.parametrize("integrator,n_md,eps", [("leapfrog", 10, 0.05), ("omelyan", 5, 0.1)])
-def test_trajectory_matches_oracle_on_a_6x6_torus(integrator, n_md, eps):
+def test_trajectory_matches_oracle_on_a_6x6_torus(integrator, n_md, eps, form):
     """Two chained trajectories on a 6 x 6 torus (72 sites), N_t = 16, with the same random numbers
-    as the oracle: the same dH, the same decision and the same field."""
-    from paper_2210_06874_amd import hmc
+    as the oracle: the same dH, the same decision and the same field, in both forms."""
+    from paper_2210_06874_amd import Hubbard, hmc
     w = Lattice("L6_Nt16", 6, 16, 2.0, 2.0)
-    print(f"[case] hmc trajectory {integrator} {w.name}", flush=True)
+    print(f"[case] hmc trajectory {integrator} {form} {w.name}", flush=True)
     phi0 = draw_weak_field(w)[0]
-    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
-    hub = _hub(w)
+    cls = O.LinearHubbardOperator if form == "linear" else O.HubbardOperator
+    op = cls(w.L, w.Nt, w.beta, w.kappa)
+    hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, form=form)
     for pi, rho, u in draw_hmc_randoms(w, 2, seed=8):
         _, _, dH_ref, acc_ref, out_ref = OH.trajectory(op, w.U, phi0, pi, rho, u, n_md=n_md, eps=eps,
                                                        integrator=integrator)
