@@ -87,8 +87,9 @@ typedef enum { HUB_FORM_EXP = 0, HUB_FORM_LINEAR = 1 } hub_form;
 typedef struct {
     int32_t L;          /* torus extent, 1 <= L <= 1024; HUB_FORM_EXP: every prime factor <= 17   */
     int32_t Nt;         /* time slices, Nt >= 1                                                 */
-    double beta;        /* inverse temperature, delta = beta/Nt                                 */
-    double kappa;       /* hopping amplitude                                                    */
+    double beta;        /* inverse temperature, delta = beta/Nt; any finite value              */
+    double kappa;       /* hopping amplitude; any finite value, either sign (with -kappa and
+                           -phi the context applies the hole operator M[-phi, -kappa], Sec. 2)  */
     int32_t nrhs_max;   /* largest nrhs any call on this context will pass, >= 1; nrhs_max * N
                            < 2^40 and each launch grid (about 2 * nrhs_max * Nt blocks) within
                            2^31 - 1, else HUB_ERR_ARG                                            */

@@ -162,7 +162,11 @@ class Hubbard:
             x = torch.empty_like(chi3)
             use_x0 = 0
         else:
-            x, _ = self._vec(x0.clone(), name="x0")
+            # the library reads the guess and writes the solution for nrhs right-hand sides
+            # through x's pointer alone, so x0 must hold exactly as many as chi
+            x, n0 = self._vec(x0.clone(), name="x0")
+            if n0 != nrhs:
+                raise ValueError(f"x0 has {n0} right-hand sides, chi has {nrhs}")
             use_x0 = 1
         hist = None
         if history:

@@ -74,8 +74,9 @@ void build_tables(const FftPlan& plan, double dk, double dmu, std::vector<double
             const double x = dk * af;
             const double c = std::cosh(x);
             double s;
-            if (x < 1e-4) {
-                // sinh(x)/x series; |f| may vanish exactly at the Dirac momenta
+            if (std::fabs(x) < 1e-4) {
+                // sinh(x)/x series (even in x, so either sign of dk); |f| may vanish exactly
+                // at the Dirac momenta
                 const double x2 = x * x;
                 s = dk * (1.0 + x2 / 6.0 * (1.0 + x2 / 20.0));
             } else {
