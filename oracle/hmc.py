@@ -9,7 +9,8 @@ second-order minimum-norm integrator of Omelyan, Mryglod and Folk (per step: mom
 by lambda*eps, field by eps/2, momentum by (1 - 2 lambda)*eps, field by eps/2, momentum
 by lambda*eps); the trajectory is accepted with probability min(1, e^{-dH}).  The operator may be either
 form of the fermion matrix (HubbardOperator or LinearHubbardOperator); the force is the
-one of that form.
+one of that form.  The normalisation of the Gaussian term is pinned by a chain without
+fermions (rho = 0), whose field variance must be delta*U (tests/test_oracle_hmc.py).
 """
 from __future__ import annotations
 

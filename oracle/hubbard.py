@@ -38,9 +38,12 @@ Conventions (readings where the paper is silent):
 
 Functions carrying no independent pin say "parity unpinned" in their docstring;
 all others are pinned by the tests in tests/test_oracle_pins.py (exponential form,
-chemical potential), tests/test_oracle_linear.py (linear form) and
-tests/test_oracle_hmc.py (trajectories), with planted mistakes in
-tests/test_oracle_mutants.py.
+chemical potential), tests/test_oracle_linear.py (linear form: the free determinant, and
+at phi != 0 the momentum blocks of a time-dependent uniform field and the determinant
+lemma for a field on one site) and tests/test_oracle_hmc.py (trajectories, and the field's
+prior variance delta*U without fermions), with planted mistakes in
+tests/test_oracle_mutants.py (both forms; the linear-form ones planted consistently in the
+dense and matrix-free operators).
 """
 from __future__ import annotations
 

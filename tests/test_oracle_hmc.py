@@ -133,3 +133,46 @@ def test_unknown_integrator_is_refused():
     w, op, phi, pi, rho, u = _setup("exp")
     with pytest.raises(ValueError):
         OH.trajectory(op, w.U, phi, pi, rho, u, n_md=2, eps=0.1, integrator="rk4")
+
+
+def _free_field_chain(n=300, seed=5):
+    """A chain with rho = 0, hence chi = 0 and no fermion action: the Hamiltonian's field part
+    alone, pi^2/2 + phi^2/(2 delta U), a harmonic oscillator of frequency 1/sqrt(delta U).  Each
+    trajectory runs a quarter period, which maps the refreshed momentum to a fresh, independent
+    field.  2 x 2 torus, N_t = 4, beta = 1, U = 2 (delta U = 0.5).  Returns the mean of phi^2 over
+    every entry of every field and its standard error from 20 batch means."""
+    w = Lattice("L2_Nt4", 2, 4, 1.0, 2.0)
+    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+    n_md = 16
+    eps = 0.5 * math.pi * math.sqrt(w.delta * w.U) / n_md
+    phi = np.zeros((w.Nt, w.V))
+    sq = []
+    for pi, rho, u in draw_hmc_randoms(w, n, seed=seed):
+        phi = OH.trajectory(op, w.U, phi, pi, 0.0 * rho, u, n_md=n_md, eps=eps)[4]
+        sq.append(np.mean(phi * phi))
+    sq = np.array(sq)
+    batches = sq.reshape(20, -1).mean(axis=1)
+    return w, sq.mean(), batches.std() / math.sqrt(20)
+
+
+def test_field_prior_variance_is_delta_u():
+    """The Gaussian term of eq. "hamiltonian" (phi^2/(2 delta U) with phi = delta times the
+    paper's field) fixes the field's variance without fermions: <phi^2> = delta U, the prior
+    std sqrt(delta U) of the workloads."""
+    w, m, se = _free_field_chain()
+    assert se < 0.02 * w.delta * w.U and abs(m - w.delta * w.U) < 5 * se, (m, se, w.delta * w.U)
+
+
+def test_field_prior_variance_detects_a_wrong_normalisation(monkeypatch):
+    """Planted consistently in the Hamiltonian and its force: phi^2/(2U) instead of
+    phi^2/(2 delta U).  The dynamics stay reversible and energy-conserving, but the chain's
+    <phi^2> becomes U, not delta U."""
+    def ham(op, U, phi, pi, chi, x):
+        return 0.5 * float(np.sum(pi * pi)) + float(np.sum(phi * phi)) / (2.0 * U) + O.action(chi, x)
+
+    def tot(op, U, phi, x):
+        return phi / U + O.force(op, phi, x)
+    monkeypatch.setattr(OH, "hamiltonian", ham)
+    monkeypatch.setattr(OH, "total_force", tot)
+    w, m, se = _free_field_chain()
+    assert abs(m - w.delta * w.U) > 5 * se, (m, se)

@@ -90,3 +90,97 @@ def test_heat_bath_and_cg():
     assert res[0] < 1e-11
     y = op.apply_Mdag(phi, x)
     assert np.linalg.norm(y - rho) <= 1e-8 * np.linalg.norm(rho)
+
+
+# ----------------------------------------------------------------------------- phi != 0 pins
+def momentum_block(L, Nt, dk, c, m1, m2):
+    """The linear operator of eq. "ferm_op" at a field phi_{t,x} = c_t (the same on every site)
+    restricted to one spatial momentum k = 2 pi (m1, m2) / L, written out from the equation
+    with time as an explicit index: a 2 Nt x 2 Nt matrix acting on (a_0..a_{Nt-1}, b_0..b_{Nt-1}),
+    the amplitudes of the plane wave e^{i k.n} on sublattices A and B.  The hopping sends a
+    plane wave on B to f(k) times it on A, and one on A to conj f(k) times it on B, with
+    f(k) = 1 + e^{-i k1} + e^{-i k2} (A(n) bonded to B(n), B(n - e1), B(n - e2));
+    the time hop across the wrap carries the antiperiodic -1."""
+    f = 1 + np.exp(-2j * np.pi * m1 / L) + np.exp(-2j * np.pi * m2 / L)
+    sign = lambda t: -1.0 if t % Nt == 0 else 1.0           # B_t: -1 on the wrap
+    blk = np.zeros((2 * Nt, 2 * Nt), dtype=complex)
+    for t in range(Nt):
+        a, b = t, Nt + t
+        # A rows: B_{t+1} a_{t+1} - e^{i c_t} a_t - dk f b_t
+        blk[a, (t + 1) % Nt] += sign(t + 1)
+        blk[a, t] -= np.exp(1j * c[t])
+        blk[a, Nt + t] -= dk * f
+        # B rows: b_t - B_t e^{-i c_t} b_{t-1} - dk conj(f) a_t
+        blk[b, Nt + t] += 1.0
+        blk[b, Nt + (t - 1) % Nt] -= sign(t) * np.exp(-1j * c[t])
+        blk[b, t] -= dk * np.conj(f)
+    return blk
+
+
+def _plane(L, m1, m2):
+    n1, n2 = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    return np.exp(2j * np.pi * ((m1 * n1 + m2 * n2) % L) / L).ravel()
+
+
+def check_uniform_field_momentum_blocks(cls=None, L=3, Nt=6, beta=2.0, seed=5):
+    """phi_{t,x} = c_t with c_t varying in time: on every plane wave in space M and M^dag act as
+    the momentum block and its adjoint, and log det M is the sum of the blocks' log dets."""
+    op = (cls or O.LinearHubbardOperator)(L, Nt, beta)
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-np.pi, np.pi, size=Nt)
+    phi = np.repeat(c[:, None], op.V, axis=1)
+    ok = True
+    ld_sum, ph_sum = 0.0, 0.0
+    for m1 in range(L):
+        for m2 in range(L):
+            blk = momentum_block(L, Nt, op.dk, c, m1, m2)
+            s, ld = np.linalg.slogdet(blk)
+            ld_sum += ld
+            ph_sum += np.angle(s)
+            ab = rng.normal(size=2 * Nt) + 1j * rng.normal(size=2 * Nt)
+            pw = _plane(L, m1, m2)
+            v = np.concatenate([ab[:Nt, None] * pw[None], ab[Nt:, None] * pw[None]], axis=1)
+            for out, mat in ((op.apply_M(phi, v[None])[0], blk), (op.apply_Mdag(phi, v[None])[0], blk.conj().T)):
+                y = mat @ ab
+                ref = np.concatenate([y[:Nt, None] * pw[None], y[Nt:, None] * pw[None]], axis=1)
+                ok &= np.abs(out - ref).max() < 1e-12 * np.abs(ref).max()
+    s, ld = np.linalg.slogdet(op.dense_M(phi))
+    ok &= abs(ld - ld_sum) < 1e-11 * max(1.0, abs(ld))
+    ok &= abs(s - np.exp(1j * ph_sum)) < 1e-10
+    return bool(ok)
+
+
+def check_single_site_phase_determinant(cls=None, L=2, Nt=5, beta=1.5):
+    """A field on one site only changes one entry of M (eq. "ferm_op": the A-site diagonal
+    -e^{i phi_{t,x}}, or the B-site hop -B_t e^{-i phi_{t,x}} from slice t-1), so by the
+    determinant lemma det M[phi] = det M[0] (1 + D (M[0]^{-1})_{c,r}) with D the change of
+    entry (r, c).  M[0] is pinned by the free determinant and the plane-wave eigenvalues."""
+    op = (cls or O.LinearHubbardOperator)(L, Nt, beta)
+    M0 = op.dense_M(np.zeros((Nt, op.V)))
+    G = np.linalg.inv(M0)
+    s0, ld0 = np.linalg.slogdet(M0)
+    ok = True
+    for (t, x, val) in [(2, 1, 0.7), (0, op.V - 1, -1.1), (Nt - 1, 0, 2.3), (3, op.nA, 0.4)]:
+        phi = np.zeros((Nt, op.V))
+        phi[t, x] = val
+        r = t * op.V + x
+        if x < op.nA:
+            c, D = r, -(np.exp(1j * val) - 1.0)
+        else:
+            Bt = -1.0 if t == 0 else 1.0
+            c, D = ((t - 1) % Nt) * op.V + x, -Bt * (np.exp(-1j * val) - 1.0)
+        s, ld = np.linalg.slogdet(op.dense_M(phi))
+        want = s0 * np.exp(ld0) * (1.0 + D * G[c, r])
+        ok &= abs(s * np.exp(ld) - want) < 1e-10 * abs(want)
+    return bool(ok)
+
+
+def test_uniform_field_momentum_blocks():
+    """A fixed fact at phi != 0 that depends on where and with which sign every phase enters."""
+    assert check_uniform_field_momentum_blocks()
+    assert check_uniform_field_momentum_blocks(L=4, Nt=5, beta=3.0, seed=7)
+
+
+def test_single_site_phase_determinant_lemma():
+    assert check_single_site_phase_determinant()
+    assert check_single_site_phase_determinant(L=3, Nt=4, beta=2.0)

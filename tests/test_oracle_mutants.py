@@ -252,3 +252,152 @@ def test_mutant_is_caught(name, monkeypatch):
             monkeypatch.setattr(O, attr, getattr(OH, attr))
         res = _run_checks()
     assert not all(res.values()), f"mutant {name} passed every check: {res}"
+
+
+# ----------------------------------------------------------------------------- linear form
+# Mistakes in the linear form of eq. "ferm_op", planted CONSISTENTLY: the mutated operator's
+# dense matrix, matrix-free M and M^dag all agree with each other (so adjointness and
+# matrix-free = dense cannot see them); only the fixed facts at phi != 0 can.
+from test_oracle_linear import check_uniform_field_momentum_blocks, check_single_site_phase_determinant
+
+_LIN = OH.LinearHubbardOperator
+
+
+def _lin_mutant(edit):
+    """A linear-form operator whose dense matrix is the oracle's with `edit` applied, and whose
+    M and M^dag are that matrix and its adjoint."""
+    class Mutant(_LIN):
+        def dense_M(self, phi):
+            M = _LIN.dense_M(self, phi)
+            edit(self, np.asarray(phi), M)
+            return M
+
+        def apply_M(self, phi, v):
+            vv, shp = self._shape(v)
+            return (vv.reshape(-1, self.N) @ self.dense_M(phi).T).reshape(shp)
+
+        def apply_Mdag(self, phi, v):
+            vv, shp = self._shape(v)
+            return (vv.reshape(-1, self.N) @ self.dense_M(phi).conj()).reshape(shp)
+    return Mutant
+
+
+def _b_hop_entries(op):
+    for t in range(op.Nt):
+        for x in range(op.nA, op.V):
+            yield t, x, t * op.V + x, ((t - 1) % op.Nt) * op.V + x
+
+
+def edit_b_phase_sign(op, phi, M):                  # e^{+i phi} on the B-site hop
+    for t, x, r, c in _b_hop_entries(op):
+        Bt = -1.0 if t == 0 else 1.0
+        M[r, c] = -Bt * np.exp(1j * phi[t, x])
+
+
+def edit_b_phase_previous_slice(op, phi, M):        # the B hop's phase taken from slice t-1
+    for t, x, r, c in _b_hop_entries(op):
+        Bt = -1.0 if t == 0 else 1.0
+        M[r, c] = -Bt * np.exp(-1j * phi[(t - 1) % op.Nt, x])
+
+
+def edit_a_wrap_sign(op, phi, M):                   # A's forward hop with B_t instead of B_{t+1}
+    for t in range(op.Nt):
+        tn = (t + 1) % op.Nt
+        for x in range(op.nA):
+            M[t * op.V + x, tn * op.V + x] = -1.0 if t == 0 else 1.0
+
+
+def edit_a_phase_conjugated(op, phi, M):            # e^{-i phi} on the A-site diagonal
+    for t in range(op.Nt):
+        for x in range(op.nA):
+            M[t * op.V + x, t * op.V + x] = -np.exp(-1j * phi[t, x])
+
+
+def edit_a_phase_next_slice(op, phi, M):            # the A diagonal's phase taken from slice t+1
+    for t in range(op.Nt):
+        for x in range(op.nA):
+            M[t * op.V + x, t * op.V + x] = -np.exp(1j * phi[(t + 1) % op.Nt, x])
+
+
+def edit_dropped_hopping(op, phi, M):               # delta*kappa dropped
+    K = op.K.toarray()
+    for t in range(op.Nt):
+        M[t * op.V:(t + 1) * op.V, t * op.V:(t + 1) * op.V] += op.dk * K
+
+
+LIN_MUTANTS = {
+    "lin_B_phase_sign": edit_b_phase_sign,
+    "lin_B_phase_previous_slice": edit_b_phase_previous_slice,
+    "lin_A_wrap_sign": edit_a_wrap_sign,
+    "lin_A_phase_conjugated": edit_a_phase_conjugated,
+    "lin_A_phase_next_slice": edit_a_phase_next_slice,
+    "lin_dropped_hopping": edit_dropped_hopping,
+}
+
+
+def _lin_fixed_facts(cls):
+    return [check_uniform_field_momentum_blocks(cls), check_single_site_phase_determinant(cls)]
+
+
+def test_linear_mutants_are_self_consistent_and_the_unmutated_form_passes():
+    """Every mutant keeps M^dag the adjoint of M (so only the fixed facts can catch it), and
+    the oracle's own linear form passes both fixed facts."""
+    assert all(_lin_fixed_facts(_LIN))
+    w = TINY
+    phi, u = draw_inputs(w, seed=1)
+    v = draw_complex(w, seed=2)
+    for edit in LIN_MUTANTS.values():
+        op = _lin_mutant(edit)(w.L, w.Nt, w.beta, w.kappa)
+        a = np.vdot(u, op.apply_M(phi, v))
+        b = np.vdot(op.apply_Mdag(phi, u), v)
+        assert abs(a - b) < 1e-12 * abs(a)
+
+
+@pytest.mark.parametrize("name", sorted(LIN_MUTANTS))
+def test_linear_mutant_is_caught_by_a_fixed_fact(name):
+    assert not all(_lin_fixed_facts(_lin_mutant(LIN_MUTANTS[name])))
+
+
+# force mistakes of the linear form, caught by finite differences of the pinned operator
+_ORIG_FORCE_LIN = OH.force_linear
+
+
+def force_linear_sign(op, phi, x):
+    return -_ORIG_FORCE_LIN(op, phi, x)
+
+
+def force_linear_b_same_slice(op, phi, x):
+    """B sites paired with y_t instead of y_{t-1}."""
+    xx = np.asarray(x, dtype=np.complex128).reshape(-1, op.Nt, op.V)
+    g = _ORIG_FORCE_LIN(op, phi, x)
+    Bs = slice(op.nA, op.V)
+    g[:, Bs] = 0.0
+    for xr in xx:
+        y = op.apply_Mdag(phi, xr)
+        g[:, Bs] += 2.0 * op.B[:, None] * (np.exp(-1j * phi[:, Bs]) * np.conj(xr[:, Bs]) * y[:, Bs]).imag
+    return g
+
+
+def check_linear_force_fd():
+    w = TINY
+    phi, chi = draw_inputs(w)
+    op = O.LinearHubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+    x = O.dense_solve_op(op, phi, chi)
+    g = OH.force_linear(op, phi, x).ravel()
+    eps = 1e-6
+    idx = pick_entries(w, 12)
+    fd = []
+    for i in idx:
+        pp = phi.ravel().copy(); pp[i] += eps
+        pm = phi.ravel().copy(); pm[i] -= eps
+        sp_ = O.action(chi, O.dense_solve_op(op, pp.reshape(phi.shape), chi))
+        sm_ = O.action(chi, O.dense_solve_op(op, pm.reshape(phi.shape), chi))
+        fd.append((sp_ - sm_) / (2 * eps))
+    return np.linalg.norm(np.array(fd) - g[idx]) <= 1e-6 * np.linalg.norm(g[idx])
+
+
+@pytest.mark.parametrize("mut", [force_linear_sign, force_linear_b_same_slice], ids=lambda f: f.__name__)
+def test_linear_force_mutant_is_caught(mut):
+    assert check_linear_force_fd()
+    with patched(OH, "force_linear", mut):
+        assert not check_linear_force_fd()
