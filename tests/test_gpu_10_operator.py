@@ -87,6 +87,52 @@ def test_apply_precision_workload(prec):
         got = to_np(hub.apply_M_c64(to_dev(p32), to_dev(v32)))
         ref = op.apply_M(p32.astype(np.float64), v32.astype(np.complex128))
         assert_close_elementwise(got, ref, RTOL32, "M32")
+        got = to_np(hub.apply_Mdag_c64(to_dev(p32), to_dev(v32)))
+        ref = op.apply_Mdag(p32.astype(np.float64), v32.astype(np.complex128))
+        assert_close_elementwise(got, ref, RTOL32, "Mdag32")
+
+
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_apply_fp32_both_operators_precision_workload(nrhs):
+    """L = 51, N_t = 128 in FP32: M and M^dag, every entry, with one right-hand side (128 slices:
+    two workgroups per slice, each writing one sublattice) and two (256 slices: one workgroup
+    per slice), against the oracle applied to the same FP32-rounded inputs."""
+    w = PREC
+    print(f"[case] apply fp32 M and Mdag {w.name} nrhs={nrhs}", flush=True)
+    phi, v = draw_inputs(w, seed=24, nrhs=nrhs)
+    hub = _hub(w, nrhs=nrhs)
+    op = oracle_op(w, mode="expm")
+    p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
+    p64, v64 = p32.astype(np.float64), v32.astype(np.complex128)
+    P, V = to_dev(p32), to_dev(v32)
+    assert_close_elementwise(to_np(hub.apply_M_c64(P, V)), op.apply_M(p64, v64), RTOL32, "M32")
+    assert_close_elementwise(to_np(hub.apply_Mdag_c64(P, V)), op.apply_Mdag(p64, v64), RTOL32, "Mdag32")
+
+
+@pytest.mark.parametrize("w", [TINY, SMALL, PREC], ids=lambda w: w.name)
+def test_negative_kappa_and_the_hole_operator(w):
+    """kappa = -1: M, M^dag (FP64 and FP32) and the force against the oracle, and the hole
+    operator M[-phi, -kappa] of the weight det(M M^dag) (Sec. 2).  A negative delta*kappa
+    exercises every branch of the E(k) table."""
+    from paper_2210_06874_amd import Hubbard
+    print(f"[case] negative kappa {w.name}", flush=True)
+    phi, v = draw_inputs(w, seed=25)
+    mode = "expm" if w.L > 20 else None
+    for sgn in (1.0, -1.0):                        # M[phi, -1] and the hole operator M[-phi, -1]
+        ph = sgn * phi
+        op = O.HubbardOperator(w.L, w.Nt, w.beta, -1.0, mode=mode)
+        hub = Hubbard(w.L, w.Nt, w.beta, -1.0)
+        P, V = to_dev(ph), to_dev(v)
+        assert_close_elementwise(to_np(hub.apply_M(P, V)), op.apply_M(ph, v), RTOL64, f"M sgn={sgn}")
+        assert_close_elementwise(to_np(hub.apply_Mdag(P, V)), op.apply_Mdag(ph, v), RTOL64, f"Mdag sgn={sgn}")
+        p32, v32 = ph.astype(np.float32), v.astype(np.complex64)
+        p64, v64 = p32.astype(np.float64), v32.astype(np.complex128)
+        assert_close_elementwise(to_np(hub.apply_M_c64(to_dev(p32), to_dev(v32))), op.apply_M(p64, v64), RTOL32,
+                                 f"M32 sgn={sgn}")
+        assert_close_elementwise(to_np(hub.apply_Mdag_c64(to_dev(p32), to_dev(v32))), op.apply_Mdag(p64, v64),
+                                 RTOL32, f"Mdag32 sgn={sgn}")
+        assert_close_elementwise(to_np(hub.force(P, V)), O.force(op, ph, v), 1e-12, f"force sgn={sgn}")
+        hub.close()
 
 
 def _stress_slices(op, phi, v, slices, dagger):
@@ -402,7 +448,7 @@ def test_context_manager_releases_the_context():
 def test_production_lengths_at_odd_shapes(L, Nt, nrhs):
     """The compile-time L = 51 and L = 102 kernels on both sides of the two-workgroup switch
     (fewer than 256 slices), with several right-hand sides, a single slice and odd N_t: M, M^dag,
-    FP32 M and the force on sampled slices against the oracle's Krylov route."""
+    FP32 M and M^dag and the force on sampled slices against the oracle's Krylov route."""
     from paper_2210_06874_amd import Hubbard
     print(f"[case] production length L={L} Nt={Nt} nrhs={nrhs}", flush=True)
     w = Lattice(f"L{L}_Nt{Nt}", L, Nt, 0.0625 * Nt, 3.9, nrhs=nrhs)
@@ -413,6 +459,7 @@ def test_production_lengths_at_odd_shapes(L, Nt, nrhs):
     M64, D64 = to_np(hub.apply_M(P, V)), to_np(hub.apply_Mdag(P, V))
     p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
     M32 = to_np(hub.apply_M_c64(to_dev(p32), to_dev(v32)))
+    D32 = to_np(hub.apply_Mdag_c64(to_dev(p32), to_dev(v32)))
     g = to_np(hub.force(P, V))
     p64, v64 = p32.astype(np.float64), v32.astype(np.complex128)
     for t in sorted({0, Nt // 2, Nt - 1}):
@@ -424,5 +471,7 @@ def test_production_lengths_at_odd_shapes(L, Nt, nrhs):
         assert_close_elementwise(D64[:, t], v[:, t] - Btn * np.exp(-1j * phi[t])[None] * wv, RTOL64, f"Mdag slice {t}")
         assert_close_elementwise(M32[:, t], v64[:, t] - Bt * op.apply_E(np.exp(1j * p64[tp])[None] * v64[:, tp]),
                                  RTOL32, f"M32 slice {t}")
+        assert_close_elementwise(D32[:, t], v64[:, t] - Btn * np.exp(-1j * p64[t])[None] * op.apply_E(v64[:, tn]),
+                                 RTOL32, f"Mdag32 slice {t}")
         gref = (-2.0 * Btn * (np.exp(1j * phi[t])[None] * v[:, t] * np.conj(wv)).imag).sum(axis=0)
         assert_close_elementwise(g[t], gref, 1e-11, f"force slice {t}")

@@ -1,5 +1,5 @@
 """A seeded sweep over random small problems: both forms, the fused and split paths, mu != 0,
-one to four right-hand sides, delta*kappa up to 1.  Every case checks M and M^dag in FP64,
+one to four right-hand sides, delta*kappa between -1 and 1.  Every case checks M and M^dag in FP64,
 M in FP32, the force on random vectors and, for the smaller ones, a mixed-precision solve, all
 against the oracle."""
 import numpy as np
@@ -25,7 +25,8 @@ def _cases(n=60, seed=2718):
         L = int(rng.choice(_FFT_L)) if form == "exp" else int(rng.integers(1, 48))
         Nt = int(rng.integers(1, 40))
         beta = float(rng.uniform(0.2, 8.0))
-        kappa = float(rng.uniform(0.0, min(2.5, Nt / beta)))      # delta * kappa <= 1
+        kmax = min(2.5, Nt / beta)                                 # |delta * kappa| <= 1
+        kappa = float(rng.uniform(-kmax, kmax))
         mu = float(rng.uniform(-0.8, 0.8)) if form == "exp" and rng.random() < 0.3 else 0.0
         path = "split" if form == "exp" and rng.random() < 0.3 else "auto"
         out.append((form, L, Nt, int(rng.integers(1, 5)), beta, kappa, mu, path))
