@@ -176,6 +176,18 @@ hub_status hub_cg_solve(hub_ctx* ctx, const double* phi, const void* chi, void* 
 hub_status hub_force(hub_ctx* ctx, const double* phi, const void* x, double* dSdphi,
                      int32_t nrhs, void* stream);
 
+/* hub_force for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same result
+ * as hub_force, bit for bit, but the per-right-hand-side forces are summed through the
+ * library's static device scratch instead of the context's buffer.  Calls no allocating
+ * routine.  The scratch holds at most 2^23 doubles (64 MiB): nrhs * N above that returns
+ * HUB_ERR_ARG (one right-hand side, or HUB_FORM_LINEAR, uses no scratch and has no limit).
+ * Every call on one GPU shares that GPU's scratch: calls that overlap in time on one GPU
+ * (from any context, stream or thread) race.  Each call writes every scratch entry it reads;
+ * nothing needs clearing. */
+hub_status hub_force_noalloc(hub_ctx* ctx, const double* phi, const void* x, double* dSdphi,
+                             int32_t nrhs, void* stream);
+
 /* S_dev[0] = sum_r Re(chi_r^dag x_r) in FP64 (the pseudofermion action of eq.
  * "hamiltonian" when x solves M M^dag x = chi).  S_dev: one double on the device. */
 hub_status hub_action(hub_ctx* ctx, const void* chi, const void* x, int32_t nrhs,

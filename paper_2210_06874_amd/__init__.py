@@ -199,6 +199,17 @@ class Hubbard:
                                           _stream_ptr(self.device)))
         return g
 
+    def force_noalloc(self, phi, x, out):
+        """hub_force_noalloc: force() into a caller-supplied `out`, with no device allocation
+        in the call (the library's static scratch sums the right-hand sides)."""
+        phi = self._phi(phi)
+        x3, nrhs = self._vec(x, name="x")
+        g = self._out(out, phi)
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_force_noalloc(self._h, self._p(phi), self._p(x3), self._p(g), nrhs,
+                                                  _stream_ptr(self.device)))
+        return g
+
     def action(self, chi, x):
         """S = sum_r Re(chi_r^dag x_r) in FP64, as a 0-dim device tensor."""
         chi3, nrhs = self._vec(chi, name="chi")

@@ -55,6 +55,7 @@ SIGNATURES = {
     "hub_apply_Mdag_c64": (_P, _P, _P, _P, _I, _P),
     "hub_cg_solve": (_P, _P, _P, _P, _I, ctypes.POINTER(HubCgOpts), ctypes.POINTER(HubCgInfo), _P),
     "hub_force": (_P, _P, _P, _P, _I, _P),
+    "hub_force_noalloc": (_P, _P, _P, _P, _I, _P),
     "hub_action": (_P, _P, _P, _I, _P, _P),
     "hub_md_update": (_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P),
     "hub_boson_energy": (_P, _P, _P, ctypes.c_double, _P, _P),

@@ -49,6 +49,29 @@ hub_status launch_check(const char* what) {
     return HUB_OK;
 }
 
+// Device scratch of hub_force_noalloc: the per-right-hand-side forces before their sum.
+// One copy per GPU, held until the process ends.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in for the symbol): hub_create looks up each
+// device's own address once, with that device current, and the entry point uses that.
+constexpr long long kNoAllocScratchDoubles = 1LL << 23;      // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// With `dev` current: look up this device's scratch address (first call per device only).
+void lookup_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_tried[dev]) return;
+    g_scratch_tried[dev] = true;
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (g_scratch_err[dev] == hipSuccess) g_scratch_ptr[dev] = static_cast<double*>(ptr);
+}
+
 // Split-path tiles: about this many complex entries per row block and per column block
 // (both sublattices), rounded to an even division of L.
 #ifndef HUB_SPLIT_ROW_ELEMS
@@ -602,6 +625,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
         return s;
     };
     if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(HUB_ERR_DEVICE, "no HIP device"));
+    lookup_scratch(c->device);      // the no-allocation entry point's scratch on this device
     if (hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
         return bail(fail(HUB_ERR_DEVICE, "cannot query LDS size"));
     c->lds_fused64 = (int)fused_lds<double>(c);
@@ -723,6 +747,26 @@ hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, in
     s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, {phi}, c->force_tmp, c->N}, CtlPlain{}, st);
     if (s != HUB_OK) return s;
     hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, c->force_tmp, g, c->N, nrhs);
+    return launch_check("k_sum_rhs");
+}
+
+hub_status hub_force_noalloc(hub_ctx* c, const double* phi, const void* x, double* g, int32_t nrhs, void* stream) {
+    hub_status s = check_vec_args(c, phi, x, g, nrhs, sizeof(cx<double>), sizeof(double), false, sizeof(double));
+    if (s != HUB_OK) return s;
+    if (c->form == HUB_FORM_LINEAR || nrhs == 1) return hub_force(c, phi, x, g, nrhs, stream);   // no scratch
+    if ((long long)nrhs * c->N > kNoAllocScratchDoubles)
+        return fail(HUB_ERR_ARG, "nrhs * N = %lld exceeds the static scratch of %lld doubles",
+                    (long long)nrhs * c->N, kNoAllocScratchDoubles);
+    double* sp = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch_ptr[c->device] : nullptr;
+    if (!sp)
+        return fail(HUB_ERR_DEVICE, "no static scratch on device %d: %s", c->device,
+                    hipGetErrorString(c->device >= 0 && c->device < kMaxDevices ? g_scratch_err[c->device]
+                                                                                 : hipErrorInvalidDevice));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const cx<double>* xv = static_cast<const cx<double>*>(x);
+    s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, {phi}, sp, c->N}, CtlPlain{}, st);
+    if (s != HUB_OK) return s;
+    hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, static_cast<const double*>(sp), g, c->N, nrhs);
     return launch_check("k_sum_rhs");
 }
 
