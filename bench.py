@@ -117,25 +117,56 @@ def time_graph(fn, per_graph: int = 50, replays: int = 10) -> float:
     return a.elapsed_time(b) * 1e-3 / (per_graph * replays)
 
 
-def cpu_baseline(w, phi, chi, budget_s: float = 15.0):
-    """The CPU oracle's operator-application rate on a bounded sample."""
+def cpu_baseline(w, phi, chi, iters_per_force: int, budget_s: float = 10.0):
+    """The CPU oracle as it stands, on the same input as the headline force step: operator
+    applications per second on a bounded sample, seconds per CG iteration from a bounded run
+    of its textbook CG, and seconds per force = the GPU FP64 solve's iteration count times that
+    plus one oracle force.  The dense-E route (E = exp(delta kappa K) from eigh, applied per
+    slice by dgemm) with every host core in BLAS; the single-threaded Krylov exp-multiply route
+    is reported beside it."""
     import threadpoolctl
     import oracle as O
-    op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa, mode="expm")
-    op.apply_M(phi, chi)                       # warm-up
-    n = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and n < 400:
-        op.apply_M(phi, chi) if n % 2 == 0 else op.apply_Mdag(phi, chi)
-        n += 1
-    dt = time.perf_counter() - t0
-    blas = threadpoolctl.threadpool_info()
-    # scipy's sparse products in expm_multiply run on one thread; numpy BLAS is not used here
-    return {"value": n / dt, "unit": "M-applications/s", "cores": 1, "kind": "oracle",
-            "s_per_cg_iteration": 2.0 * dt / n,
-            "sample": f"{n} alternating M / M^dag applications at L=51 Nt=128 (Krylov exp-multiply "
-                      f"route, FP64), {dt:.1f} s; host has {os.cpu_count()} cores, BLAS "
-                      f"{blas[0]['internal_api'] if blas else 'none'} unused"}
+    ncpu = os.cpu_count() or 1
+    with threadpoolctl.threadpool_limits(limits=ncpu, user_api="blas"):
+        blas = [dict(api=i["internal_api"], threads=i["num_threads"], version=i.get("version"))
+                for i in threadpoolctl.threadpool_info() if i["user_api"] == "blas"]
+        t_setup = time.perf_counter()
+        op = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa, mode="dense-E")
+        t_setup = time.perf_counter() - t_setup
+        op.apply_M(phi, chi)                       # warm-up
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s and n < 400:
+            op.apply_M(phi, chi) if n % 2 == 0 else op.apply_Mdag(phi, chi)
+            n += 1
+        dt = time.perf_counter() - t0
+        # the oracle's own CG for a bounded number of iterations (each: M^dag, M, vector updates)
+        k = max(4, min(100, int(budget_s / max(1e-3, 2.0 * dt / n))))
+        t1 = time.perf_counter()
+        O.cg_solve(op, phi, chi, tol=1e-10, max_iter=k)
+        t_cg = time.perf_counter() - t1
+        x = chi                                    # any vector: the force's cost does not depend on it
+        t2 = time.perf_counter()
+        O.force(op, phi, x)
+        t_force = time.perf_counter() - t2
+    # includes the final true-residual check (one more M M^dag) in k iterations' time
+    s_it = t_cg / (k + 1)
+    t3 = time.perf_counter()
+    m = 0
+    opk = O.HubbardOperator(w.L, w.Nt, w.beta, w.kappa, mode="expm")
+    while time.perf_counter() - t3 < 0.5 * budget_s and m < 100:
+        opk.apply_M(phi, chi)
+        m += 1
+    krylov = m / (time.perf_counter() - t3)
+    return {"value": n / dt, "unit": "M-applications/s", "cores": ncpu, "kind": "oracle",
+            "s_per_cg_iteration": s_it, "s_per_force": iters_per_force * s_it + t_force,
+            "s_per_force_basis": f"{iters_per_force} iterations (the GPU FP64 solve of the same input) "
+                                 f"x s per oracle CG iteration + one oracle force ({t_force:.2f} s)",
+            "blas": blas, "setup_s_eigh": t_setup,
+            "krylov_route_1_thread_M_applications_per_s": krylov,
+            "sample": f"{n} alternating M / M^dag applications ({dt:.1f} s) and {k} CG iterations "
+                      f"({t_cg:.1f} s) of the FP64 oracle at L={w.L} Nt={w.Nt} on the headline input, "
+                      f"dense-E route, BLAS on {ncpu} threads"}
 
 
 def nrhs_scan(w, dev) -> dict:
@@ -415,8 +446,7 @@ def main() -> int:
         "cpu_baseline": None,
     }
     if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
-        phi_l, chi_l = draw_inputs(w)
-        line["cpu_baseline"] = cpu_baseline(w, phi_l, chi_l)
+        line["cpu_baseline"] = cpu_baseline(w, phi_w, chi_w, res64.iters[0])
     print(json.dumps(line))
     return 0
 
