@@ -147,6 +147,30 @@ hub_status hub_apply_M_c64(hub_ctx* ctx, const float* phi, const void* in, void*
 hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,
                               int32_t nrhs, void* stream);
 
+/* Time slabs: the operators and the force on one shard of a time-sharded vector (the layout a
+ * run that splits the Nt slices over several GPUs gives each of them; Sec. 2 operator,
+ * HUB_FORM_EXP only, else HUB_ERR_ARG).  The slab is the nt consecutive slices t0 .. t0+nt-1 of
+ * the context's Nt (0 <= t0, nt >= 1, t0 + nt <= Nt); its arrays hold those slices only:
+ *     phi: double [nt][V] (float for _c64),  in, out, x: complex [nrhs][nt][V],  dSdphi: double [nt][V].
+ * The one slice each needs from beyond the slab is passed as a halo (what a neighbouring shard
+ * would send), one slice per right-hand side, complex [nrhs][V]:
+ *     hub_apply_M_slab:    in_halo = v at slice (t0 - 1) mod Nt, phi_halo (double [V]) = phi there;
+ *     hub_apply_Mdag_slab: in_halo = v at slice (t0 + nt) mod Nt;
+ *     hub_force_slab:      x_halo  = x at slice (t0 + nt) mod Nt.
+ * Row t of the output is row t0 + t of the full operator (or force); with t0 = 0, nt = Nt and the
+ * halo taken from the vector itself the calls reproduce hub_apply_M, hub_apply_Mdag and hub_force.
+ * The antiperiodic sign follows the global slice index.  out may overlap no input or halo. */
+hub_status hub_apply_M_slab(hub_ctx* ctx, int32_t t0, int32_t nt, const double* phi, const void* in,
+                            const double* phi_halo, const void* in_halo, void* out, int32_t nrhs, void* stream);
+hub_status hub_apply_Mdag_slab(hub_ctx* ctx, int32_t t0, int32_t nt, const double* phi, const void* in,
+                               const void* in_halo, void* out, int32_t nrhs, void* stream);
+hub_status hub_apply_M_slab_c64(hub_ctx* ctx, int32_t t0, int32_t nt, const float* phi, const void* in,
+                                const float* phi_halo, const void* in_halo, void* out, int32_t nrhs, void* stream);
+hub_status hub_apply_Mdag_slab_c64(hub_ctx* ctx, int32_t t0, int32_t nt, const float* phi, const void* in,
+                                   const void* in_halo, void* out, int32_t nrhs, void* stream);
+hub_status hub_force_slab(hub_ctx* ctx, int32_t t0, int32_t nt, const double* phi, const void* x,
+                          const void* x_halo, double* dSdphi, int32_t nrhs, void* stream);
+
 /* Solve (M M^dag) x = chi for nrhs independent right-hand sides (Sec. 2, eq.
  * "hamiltonian": the pseudofermion term needs (M M^dag)^{-1} chi).  Conjugate
  * gradients from x0 = 0 (or x on entry when opts->use_x0), all reductions in FP64.

@@ -147,6 +147,68 @@ class Hubbard:
         """M[phi]^dag v in FP32."""
         return self._apply(self.lib.hub_apply_Mdag_c64, phi32, v, torch.complex64, torch.float32, out)
 
+    # ------------------------------------------------------------------ time slabs
+    def _slab_args(self, t0, phi, v, halo, cdtype, rdtype, phi_halo=None, name="in"):
+        if not isinstance(phi, torch.Tensor) or phi.device != self.device or phi.dtype != rdtype \
+                or phi.dim() != 2 or phi.shape[1] != self.V or not phi.is_contiguous():
+            raise ValueError(f"phi must be a contiguous {rdtype} tensor [nt, {self.V}] on {self.device}")
+        nt = phi.shape[0]
+        if not isinstance(v, torch.Tensor) or v.device != self.device or v.dtype != cdtype:
+            raise ValueError(f"{name} must be a {cdtype} tensor on {self.device}")
+        v3 = v.unsqueeze(0) if v.dim() == 2 else v
+        if v3.dim() != 3 or tuple(v3.shape[1:]) != (nt, self.V) or not v3.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape [nrhs, {nt}, {self.V}]")
+        nrhs = v3.shape[0]
+        if not isinstance(halo, torch.Tensor) or halo.device != self.device or halo.dtype != cdtype \
+                or halo.numel() != nrhs * self.V or not halo.is_contiguous():
+            raise ValueError(f"the halo must be a contiguous {cdtype} tensor of {nrhs} x {self.V} entries")
+        if phi_halo is not None and (not isinstance(phi_halo, torch.Tensor) or phi_halo.device != self.device
+                                     or phi_halo.dtype != rdtype or phi_halo.numel() != self.V
+                                     or not phi_halo.is_contiguous()):
+            raise ValueError(f"phi_halo must be a contiguous {rdtype} tensor of {self.V} entries")
+        if not (0 <= int(t0) and int(t0) + nt <= self.Nt):
+            raise ValueError(f"slab t0={t0} nt={nt} outside the {self.Nt} slices")
+        return nt, v3, nrhs
+
+    def _slab_apply(self, fn, t0, phi, v, halo, cdtype, rdtype, phi_halo=None):
+        nt, v3, nrhs = self._slab_args(t0, phi, v, halo, cdtype, rdtype, phi_halo)
+        o = torch.empty_like(v3)
+        args = [self._h, int(t0), nt, self._p(phi), self._p(v3)]
+        if phi_halo is not None:
+            args.append(self._p(phi_halo))
+        args += [self._p(halo), self._p(o), nrhs, _stream_ptr(self.device)]
+        with torch.cuda.device(self.device):
+            _lib.check(fn(*args))
+        return o if v.dim() == 3 else o[0]
+
+    def apply_M_slab(self, t0, phi, v, phi_halo, v_halo):
+        """Rows t0 .. t0+nt-1 of M v from the slab's slices (phi [nt, V], v [nrhs, nt, V]) and
+        the halo slice t0-1: phi_halo [V], v_halo [nrhs, V] (FP64)."""
+        return self._slab_apply(self.lib.hub_apply_M_slab, t0, phi, v, v_halo, torch.complex128, torch.float64,
+                                phi_halo)
+
+    def apply_Mdag_slab(self, t0, phi, v, v_halo):
+        """Rows t0 .. t0+nt-1 of M^dag v; v_halo [nrhs, V] is slice t0+nt (mod Nt) (FP64)."""
+        return self._slab_apply(self.lib.hub_apply_Mdag_slab, t0, phi, v, v_halo, torch.complex128, torch.float64)
+
+    def apply_M_slab_c64(self, t0, phi32, v, phi_halo, v_halo):
+        return self._slab_apply(self.lib.hub_apply_M_slab_c64, t0, phi32, v, v_halo, torch.complex64,
+                                torch.float32, phi_halo)
+
+    def apply_Mdag_slab_c64(self, t0, phi32, v, v_halo):
+        return self._slab_apply(self.lib.hub_apply_Mdag_slab_c64, t0, phi32, v, v_halo, torch.complex64,
+                                torch.float32)
+
+    def force_slab(self, t0, phi, x, x_halo):
+        """Rows t0 .. t0+nt-1 of dS/dphi from the slab's solutions x [nrhs, nt, V] and x at slice
+        t0+nt (mod Nt), x_halo [nrhs, V]."""
+        nt, x3, nrhs = self._slab_args(t0, phi, x, x_halo, torch.complex128, torch.float64, name="x")
+        g = torch.empty((nt, self.V), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_force_slab(self._h, int(t0), nt, self._p(phi), self._p(x3), self._p(x_halo),
+                                               self._p(g), nrhs, _stream_ptr(self.device)))
+        return g
+
     # ------------------------------------------------------------------ solver, action, force
     def cg_solve(self, phi, chi, tol: float = 1e-10, max_iter: int = 100000, prec: str = "fp64",
                  reliable_every: int = 50, x0=None, raise_on_error: bool = True,

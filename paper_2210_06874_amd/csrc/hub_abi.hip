@@ -349,6 +349,65 @@ hub_status apply_Mdag_impl(hub_ctx* c, const R* phi, const void* in, void* out, 
                      CtlPlain{}, static_cast<hipStream_t>(stream));
 }
 
+// ----------------------------------------------------------------------------- time slabs
+// A view of the context over the nt slices of one time slab: the kernels index vectors by the
+// slab's own slices, while the tables and buffers stay the context's (its buffers hold at least
+// nrhs_max * N >= nrhs * nt * V entries).
+hub_ctx slab_view(const hub_ctx* c, int nt) {
+    hub_ctx v = *c;
+    v.Nt = nt;
+    v.N = (long long)nt * c->V;
+    return v;
+}
+
+// Slab arguments: 0 <= t0, nt >= 1, t0 + nt <= Nt; arrays as in check_vec_args with nt slices;
+// the halo ([nrhs][V] entries of `elem` bytes, and phi_halo [V] when given) may not overlap out.
+hub_status check_slab_args(const hub_ctx* c, int t0, int nt, const void* phi, size_t phi_elem, const void* in,
+                           size_t elem, const void* halo, const void* phi_halo, bool need_phi_halo, const void* out,
+                           size_t out_elem, bool out_per_rhs, int nrhs) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (c->form != HUB_FORM_EXP) return fail(HUB_ERR_ARG, "time slabs are available for HUB_FORM_EXP only");
+    if (t0 < 0 || nt < 1 || (long long)t0 + nt > c->Nt)
+        return fail(HUB_ERR_ARG, "slab t0=%d nt=%d outside [0, Nt=%d]", t0, nt, c->Nt);
+    if (!phi || !in || !halo || !out || (need_phi_halo && !phi_halo)) return fail(HUB_ERR_ARG, "NULL array argument");
+    if (nrhs < 1 || nrhs > c->nrhs_max)
+        return fail(HUB_ERR_ARG, "nrhs=%d outside [1, nrhs_max=%d]", nrhs, c->nrhs_max);
+    const size_t ns = (size_t)nt * c->V;
+    const size_t out_bytes = (size_t)(out_per_rhs ? nrhs : 1) * ns * out_elem;
+    if (overlaps(in, (size_t)nrhs * ns * elem, out, out_bytes)) return fail(HUB_ERR_ARG, "input and output overlap");
+    if (overlaps(phi, ns * phi_elem, out, out_bytes)) return fail(HUB_ERR_ARG, "phi and output overlap");
+    if (overlaps(halo, (size_t)nrhs * c->V * elem, out, out_bytes)) return fail(HUB_ERR_ARG, "halo and output overlap");
+    if (need_phi_halo && overlaps(phi_halo, (size_t)c->V * phi_elem, out, out_bytes))
+        return fail(HUB_ERR_ARG, "phi halo and output overlap");
+    return check_device(c);
+}
+
+template <typename R>
+hub_status apply_M_slab_impl(hub_ctx* c, int t0, int nt, const R* phi, const void* in, const R* phi_halo,
+                             const void* in_halo, void* out, int nrhs, void* stream) {
+    hub_status s = check_slab_args(c, t0, nt, phi, sizeof(R), in, sizeof(cx<R>), in_halo, phi_halo, true, out,
+                                   sizeof(cx<R>), true, nrhs);
+    if (s != HUB_OK) return s;
+    hub_ctx view = slab_view(c, nt);
+    const cx<R>* v = static_cast<const cx<R>*>(in);
+    return run_op<R>(&view, nrhs,
+                     SrcPhasePrevSlab<R>{v, PhAngle<R>{phi}, static_cast<const cx<R>*>(in_halo), PhAngle<R>{phi_halo}},
+                     EpiMSlab<R>{v, static_cast<cx<R>*>(out), t0}, CtlPlain{}, static_cast<hipStream_t>(stream));
+}
+
+template <typename R>
+hub_status apply_Mdag_slab_impl(hub_ctx* c, int t0, int nt, const R* phi, const void* in, const void* in_halo,
+                                void* out, int nrhs, void* stream) {
+    hub_status s = check_slab_args(c, t0, nt, phi, sizeof(R), in, sizeof(cx<R>), in_halo, nullptr, false, out,
+                                   sizeof(cx<R>), true, nrhs);
+    if (s != HUB_OK) return s;
+    hub_ctx view = slab_view(c, nt);
+    const cx<R>* v = static_cast<const cx<R>*>(in);
+    return run_op<R>(&view, nrhs, SrcNextSlab<R>{v, static_cast<const cx<R>*>(in_halo)},
+                     EpiMdagSlab<R>{v, static_cast<cx<R>*>(out), PhAngle<R>{phi}, t0, c->Nt}, CtlPlain{},
+                     static_cast<hipStream_t>(stream));
+}
+
 // Solver workspace, allocated on the first solve.  After a failed allocation the
 // buffers already obtained stay with the context (hub_destroy frees them) and a later
 // call allocates only the missing ones.
@@ -747,6 +806,40 @@ hub_status hub_force(hub_ctx* c, const double* phi, const void* x, double* g, in
     s = run_op<double>(c, nrhs, SrcNext<double>{xv}, EpiForce{xv, {phi}, c->force_tmp, c->N}, CtlPlain{}, st);
     if (s != HUB_OK) return s;
     hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, c->force_tmp, g, c->N, nrhs);
+    return launch_check("k_sum_rhs");
+}
+
+hub_status hub_apply_M_slab(hub_ctx* c, int32_t t0, int32_t nt, const double* phi, const void* in,
+                            const double* phi_halo, const void* in_halo, void* out, int32_t nrhs, void* st) {
+    return apply_M_slab_impl<double>(c, t0, nt, phi, in, phi_halo, in_halo, out, nrhs, st);
+}
+hub_status hub_apply_Mdag_slab(hub_ctx* c, int32_t t0, int32_t nt, const double* phi, const void* in,
+                               const void* in_halo, void* out, int32_t nrhs, void* st) {
+    return apply_Mdag_slab_impl<double>(c, t0, nt, phi, in, in_halo, out, nrhs, st);
+}
+hub_status hub_apply_M_slab_c64(hub_ctx* c, int32_t t0, int32_t nt, const float* phi, const void* in,
+                                const float* phi_halo, const void* in_halo, void* out, int32_t nrhs, void* st) {
+    return apply_M_slab_impl<float>(c, t0, nt, phi, in, phi_halo, in_halo, out, nrhs, st);
+}
+hub_status hub_apply_Mdag_slab_c64(hub_ctx* c, int32_t t0, int32_t nt, const float* phi, const void* in,
+                                   const void* in_halo, void* out, int32_t nrhs, void* st) {
+    return apply_Mdag_slab_impl<float>(c, t0, nt, phi, in, in_halo, out, nrhs, st);
+}
+
+hub_status hub_force_slab(hub_ctx* c, int32_t t0, int32_t nt, const double* phi, const void* x,
+                          const void* x_halo, double* g, int32_t nrhs, void* stream) {
+    hub_status s = check_slab_args(c, t0, nt, phi, sizeof(double), x, sizeof(cx<double>), x_halo, nullptr, false, g,
+                                   sizeof(double), false, nrhs);
+    if (s != HUB_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hub_ctx view = slab_view(c, nt);
+    const cx<double>* xv = static_cast<const cx<double>*>(x);
+    const SrcNextSlab<double> src{xv, static_cast<const cx<double>*>(x_halo)};
+    if (nrhs == 1) return run_op<double>(&view, 1, src, EpiForceSlab{xv, {phi}, g, 0, t0, c->Nt}, CtlPlain{}, st);
+    s = run_op<double>(&view, nrhs, src, EpiForceSlab{xv, {phi}, c->force_tmp, view.N, t0, c->Nt}, CtlPlain{}, st);
+    if (s != HUB_OK) return s;
+    hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, static_cast<const double*>(c->force_tmp), g,
+                       view.N, nrhs);
     return launch_check("k_sum_rhs");
 }
 

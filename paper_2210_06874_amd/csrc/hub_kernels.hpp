@@ -380,6 +380,93 @@ struct EpiForce {                // g_t = -2 B_{t+1} Im(e^{i phi_t} x_t conj(w))
     }
 };
 
+// ----------------------------------------------------------------------------- time slabs
+// One shard of a time-sharded vector: the kernels run over the slab's nt slices (OpTab's
+// Nt and N are the slab's), the slice across the slab's edge comes from a halo buffer
+// ([nrhs][V], one slice per right-hand side), and the antiperiodic sign is taken at the
+// global slice t0 + t of a lattice of Ntg slices.  The halo branch is uniform per block.
+template <typename R, class Ph = PhAngle<R>>
+struct SrcPhasePrevSlab {        // e^{i phi_{t-1}} v_{t-1}; slab slice -1 is the halo (M)
+    using Pre = PrePh<R, Ph>;
+    const cx<R>* v;
+    Ph ph;
+    const cx<R>* vh;             // v at global slice t0 - 1
+    Ph phh;                      // phi at global slice t0 - 1
+    __device__ int slice(int t, int) const { return t - 1; }
+    __device__ Pre fetch(int rhs, int ts, int i, const OpTab<R>& T) const {
+        if (ts < 0) return {vh[(long long)rhs * T.V + i], phh.fetch(i)};
+        const long long k = (long long)ts * T.V + i;
+        return {v[rhs * T.N + k], ph.fetch(k)};
+    }
+    __device__ cx<R> make(const Pre& a, const Scal&) const { return cmul(a.v, ph.value(a.ph)); }
+};
+
+template <typename R>
+struct SrcNextSlab {             // v_{t+1}; slab slice nt is the halo (M^dag, force)
+    using Pre = cx<R>;
+    const cx<R>* v;
+    const cx<R>* vh;             // v at global slice t0 + nt
+    __device__ int slice(int t, int) const { return t + 1; }
+    __device__ Pre fetch(int rhs, int ts, int i, const OpTab<R>& T) const {
+        if (ts >= T.Nt) return vh[(long long)rhs * T.V + i];
+        return v[rhs * T.N + (long long)ts * T.V + i];
+    }
+    __device__ cx<R> make(const Pre& a, const Scal&) const { return a; }
+};
+
+template <typename R>
+struct EpiMSlab {                // out_t = v_t - B_{t0+t} w
+    using Pre = cx<R>;
+    const cx<R>* v;
+    cx<R>* out;
+    int t0;
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
+        return v[rhs * T.N + (long long)t * T.V + i];
+    }
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, const Scal&,
+                          double&) const {
+        out[rhs * T.N + (long long)t * T.V + i] = (t0 + t == 0) ? a + w : a - w;
+    }
+};
+
+template <typename R>
+struct EpiMdagSlab {             // out_t = v_t - B_{t0+t+1} e^{-i phi_t} w
+    using Pre = PrePh<R, PhAngle<R>>;
+    const cx<R>* v;
+    cx<R>* out;
+    PhAngle<R> ph;
+    int t0, Ntg;
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
+        const long long ks = (long long)t * T.V + i;
+        return {v[rhs * T.N + ks], ph.fetch(ks)};
+    }
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, const Scal&,
+                          double&) const {
+        const cx<R> pw = cmulc(w, ph.value(a.ph));
+        out[rhs * T.N + (long long)t * T.V + i] = (t0 + t == Ntg - 1) ? a.v + pw : a.v - pw;
+    }
+};
+
+struct EpiForceSlab {            // g_t = -2 B_{t0+t+1} Im(e^{i phi_t} x_t conj(w)),  w = (E x_{t+1})
+    using Pre = PrePh<double, PhAngle<double>>;
+    const cx<double>* x;
+    PhAngle<double> ph;
+    double* g;                   // [nrhs or 1][nt][V]
+    long long g_rhs_stride;      // 0 when there is one right-hand side
+    int t0, Ntg;
+    __device__ Pre fetch(int rhs, int t, int i, const OpTab<double>& T) const {
+        const long long ks = (long long)t * T.V + i;
+        return {x[rhs * T.N + ks], ph.fetch(ks)};
+    }
+    __device__ void store(int rhs, int t, int i, cx<double> w, const Pre& a, const OpTab<double>& T, const Scal&,
+                          double&) const {
+        const long long ks = (long long)t * T.V + i;
+        const cx<double> z = cmulc(cmul(a.v, ph.value(a.ph)), w);
+        const double bn = (t0 + t == Ntg - 1) ? -1.0 : 1.0;
+        g[rhs * g_rhs_stride + ks] = -2.0 * bn * z.im;
+    }
+};
+
 // fetch + store in one call (kernels that do not prefetch)
 template <typename R, class Epi>
 __device__ __forceinline__ void epi_apply(const Epi& epi, int rhs, int t, int i, cx<R> w, const OpTab<R>& T,
