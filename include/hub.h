@@ -36,7 +36,8 @@
  * owned by the caller; the library keeps no pointer after a call returns.  The
  * context owns its tables and workspace: hub_create allocates the tables, the
  * reduction partials and the operator scratch, the first hub_cg_solve the solver
- * vectors, the first hub_trajectory its own vectors; nothing else allocates;
+ * vectors, the first hub_trajectory its own vectors, the first hub_log_det its two
+ * matrices; nothing else allocates;
  * hub_destroy frees all of it.
  *
  * Streams: every call enqueues its work on `stream` (a hipStream_t; NULL means
@@ -262,6 +263,19 @@ typedef struct {
  * the context; the call synchronises on `stream` (each solve reads its status). */
 hub_status hub_trajectory(hub_ctx* ctx, double* phi, const double* pi0, const void* rho, int32_t nrhs,
                           double u, const hub_traj_opts* opts, hub_traj_info* info_host, void* stream);
+
+/* log det M[phi] of the exponential form with the context's kappa and mu (Sec. 2; Sec. 3: the
+ * weight away from half filling is det(M[phi,mu] M[phi,-mu]^dag) = det M[phi,mu] conj det
+ * M[phi,-mu], so its phase theta, the reweighting factor e^{i theta}, is the difference of the
+ * arguments from two contexts at +mu and -mu).  Computed as det(1 + E D_{Nt-1} ... E D_0), the
+ * block-cyclic identity of the antiperiodic operator: the transfer product is applied slice by
+ * slice to the V columns of the identity with the library's own E kernels, then one workgroup
+ * takes an LU with partial pivoting in FP64.  out_dev (two doubles on the device): out_dev[0] =
+ * log|det M| (-inf for a singular product), out_dev[1] = arg det M in (-pi, pi].  Small lattices:
+ * V <= 1152 (L <= 24) and |beta| (3|kappa| + |mu|) <= 29 (the product is not stabilised), else
+ * HUB_ERR_ARG; HUB_FORM_EXP only.  The first call allocates two V x V complex128 matrices in the
+ * context.  Stream-ordered, no synchronisation. */
+hub_status hub_log_det(hub_ctx* ctx, const double* phi, double* out_dev, void* stream);
 
 /* Report the kernel path the context uses (hub_path value, never AUTO) and the
  * LDS bytes per workgroup of its operator kernel (HUB_FORM_LINEAR: FUSED and 0, one

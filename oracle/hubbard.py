@@ -57,7 +57,7 @@ __all__ = [
     "site_index", "honeycomb_bonds", "hopping_matrix", "hopping_matrix_sparse",
     "hopping_exponential", "antiperiodic_signs", "HubbardOperator", "LinearHubbardOperator",
     "cg_solve", "dense_solve", "action", "force", "force_dense", "force_linear",
-    "force_dense_linear", "dense_solve_op",
+    "force_dense_linear", "dense_solve_op", "log_det", "sign_phase", "reweight",
 ]
 
 
@@ -423,3 +423,33 @@ def dense_solve_op(op, phi, chi):
     A = M @ M.conj().T
     chi = np.asarray(chi, dtype=np.complex128).reshape(-1, op.N)
     return np.linalg.solve(A, chi.T).T.reshape(-1, op.Nt, op.V)
+
+
+# --------------------------------------------------------------------------- Sec. 3 weight
+def log_det(op: HubbardOperator, phi: np.ndarray) -> tuple[float, float]:
+    """(log|det M[phi]|, arg det M[phi]) of the exponential form, from the block-cyclic identity
+    det M = det(1 + E D_{Nt-1} ... E D_0) (antiperiodic wrap): the product is built slice by
+    slice with the dense E and its determinant taken by LU (numpy's slogdet).  Tiny and small
+    lattices (dense V x V); the product is not stabilised, so beta (3|kappa| + |mu|) must stay
+    moderate.  The argument is reduced to (-pi, pi]."""
+    if op.E is None:
+        raise ValueError("log_det needs mode dense-E")
+    P = np.eye(op.V, dtype=complex)
+    for t in range(op.Nt):
+        P = op.E @ (np.exp(1j * phi[t])[:, None] * P)
+    s, ld = np.linalg.slogdet(np.eye(op.V) + P)
+    return float(ld), float(np.angle(s))
+
+
+def sign_phase(op_plus: HubbardOperator, op_minus: HubbardOperator, phi: np.ndarray) -> float:
+    """theta of Sec. 3: the weight det(M[phi, mu] M[phi, -mu]^dag) = |p| e^{i theta}, so
+    theta = arg det M[phi, mu] - arg det M[phi, -mu], reduced to (-pi, pi]."""
+    a = log_det(op_plus, phi)[1] - log_det(op_minus, phi)[1]
+    return float(np.angle(np.exp(1j * a)))
+
+
+def reweight(obs: np.ndarray, theta: np.ndarray) -> complex:
+    """Sec. 3 reweighting: <O>_p = <O e^{i theta}>_|p| / <e^{i theta}>_|p| over samples drawn
+    with the weight |p|."""
+    z = np.exp(1j * np.asarray(theta, dtype=float))
+    return complex(np.mean(np.asarray(obs) * z) / np.mean(z))

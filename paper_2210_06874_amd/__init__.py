@@ -16,13 +16,21 @@ import torch
 from . import _lib
 from ._lib import HubError, HUB_OK
 
-__all__ = ["Hubbard", "CgResult", "HubError", "PseudofermionAction"]
+__all__ = ["Hubbard", "CgResult", "HubError", "PseudofermionAction", "reweight"]
 
 _PREC = {"fp64": _lib.HUB_PREC_FP64, "mixed": _lib.HUB_PREC_MIXED}
 _PATH = {"auto": _lib.HUB_PATH_AUTO, "fused": _lib.HUB_PATH_FUSED, "split": _lib.HUB_PATH_SPLIT}
 _PATH_NAME = {v: k for k, v in _PATH.items()}
 _FORM = {"exp": _lib.HUB_FORM_EXP, "linear": _lib.HUB_FORM_LINEAR}
 _INTEGRATOR = {"leapfrog": _lib.HUB_MD_LEAPFROG, "omelyan": _lib.HUB_MD_OMELYAN}
+
+
+def reweight(obs, theta) -> complex:
+    """Sec. 3 reweighting of samples drawn with the weight |p|: <O>_p = <O e^{i theta}> / <e^{i theta}>,
+    from per-sample observables and phases theta (Hubbard.sign_phase); host-side statistics."""
+    import numpy as np
+    z = np.exp(1j * np.asarray(theta, dtype=float))
+    return complex(np.mean(np.asarray(obs) * z) / np.mean(z))
 
 
 def _stream_ptr(device) -> ctypes.c_void_p:
@@ -284,6 +292,22 @@ class Hubbard:
                                            _stream_ptr(self.device)))
         return S
 
+
+    # ------------------------------------------------------------------ Sec. 3 weight
+    def log_det(self, phi) -> torch.Tensor:
+        """(log|det M[phi]|, arg det M[phi]) as a float64 device tensor [2] (hub_log_det)."""
+        phi = self._phi(phi)
+        out = torch.empty(2, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.hub_log_det(self._h, self._p(phi), self._p(out), _stream_ptr(self.device)))
+        return out
+
+    def sign_phase(self, hole: "Hubbard", phi) -> float:
+        """theta of the Sec. 3 weight det(M[phi,mu] M[phi,-mu]^dag) = |p| e^{i theta}: this context
+        holds +mu, `hole` the same lattice at -mu; theta = arg det M[phi,mu] - arg det M[phi,-mu],
+        reduced to (-pi, pi]."""
+        a = self.log_det(phi)[1] - hole.log_det(phi)[1]
+        return float(torch.atan2(torch.sin(a), torch.cos(a)))
 
     # ------------------------------------------------------------------ HMC pieces
     def md_update(self, phi, pi, dSdphi, U: float, eps_pi: float, eps_phi: float):

@@ -56,6 +56,7 @@ SIGNATURES = {
     "hub_cg_solve": (_P, _P, _P, _P, _I, ctypes.POINTER(HubCgOpts), ctypes.POINTER(HubCgInfo), _P),
     "hub_force": (_P, _P, _P, _P, _I, _P),
     "hub_force_noalloc": (_P, _P, _P, _P, _I, _P),
+    "hub_log_det": (_P, _P, _P, _P),
     "hub_apply_M_slab": (_P, _I, _I, _P, _P, _P, _P, _P, _I, _P),
     "hub_apply_Mdag_slab": (_P, _I, _I, _P, _P, _P, _P, _I, _P),
     "hub_apply_M_slab_c64": (_P, _I, _I, _P, _P, _P, _P, _P, _I, _P),

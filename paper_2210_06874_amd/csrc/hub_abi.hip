@@ -72,6 +72,12 @@ void lookup_scratch(int dev) {
     if (g_scratch_err[dev] == hipSuccess) g_scratch_ptr[dev] = static_cast<double*>(ptr);
 }
 
+// hub_log_det: dense V x V limit (L <= 24), and the largest |beta| (3|kappa| + |mu|) it accepts.
+// That is the log of the bound on the transfer product's largest singular value; the product's
+// roundoff grows like 2^-53 e^{that}, about 4e-4 of its largest entry at 29.
+constexpr int kLogDetMaxV = 1152;
+constexpr double kLogDetMaxGrowth = 29.0;
+
 // Split-path tiles: about this many complex entries per row block and per column block
 // (both sublattices), rounded to an even division of L.
 #ifndef HUB_SPLIT_ROW_ELEMS
@@ -676,6 +682,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     c->nrhs_max = prm->nrhs_max;
     c->beta = prm->beta;
     c->kappa = prm->kappa;
+    c->mu = prm->mu;
     c->delta = prm->beta / prm->Nt;
     c->plan = plan;
     c->form = prm->form;
@@ -746,7 +753,7 @@ void hub_destroy(hub_ctx* c) {
     void* dev[] = {c->roots64, c->roots32, c->etab64, c->etab32, c->partials, c->counters, c->red_out,
                    c->split_w, c->cg_rhi, c->cg_tmp, c->cg_x, c->cg_r, c->cg_p, c->cg_t,
                    c->ph64, c->ph32, c->scal, c->cg_pr, c->cg_pt, c->force_tmp,
-                   c->tr_chi, c->tr_x, c->tr_pi, c->tr_phi0, c->tr_g, c->tr_E};
+                   c->tr_chi, c->tr_x, c->tr_pi, c->tr_phi0, c->tr_g, c->tr_E, c->ld_x, c->ld_y};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->scal_host) (void)hipHostFree(c->scal_host);
@@ -861,6 +868,45 @@ hub_status hub_force_noalloc(hub_ctx* c, const double* phi, const void* x, doubl
     if (s != HUB_OK) return s;
     hipLaunchKernelGGL(k_sum_rhs, dim3(1024), dim3(kThreads), 0, st, static_cast<const double*>(sp), g, c->N, nrhs);
     return launch_check("k_sum_rhs");
+}
+
+hub_status hub_log_det(hub_ctx* c, const double* phi, double* out_dev, void* stream) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (!phi || !out_dev) return fail(HUB_ERR_ARG, "NULL array argument");
+    if (c->form != HUB_FORM_EXP) return fail(HUB_ERR_ARG, "hub_log_det is available for HUB_FORM_EXP only");
+    if (c->V > kLogDetMaxV) return fail(HUB_ERR_ARG, "V=%d above the dense limit %d of hub_log_det", c->V, kLogDetMaxV);
+    const double growth = std::fabs(c->beta) * (3.0 * std::fabs(c->kappa) + std::fabs(c->mu));
+    if (growth > kLogDetMaxGrowth)
+        return fail(HUB_ERR_ARG, "|beta| (3|kappa| + |mu|) = %g above %g: the unstabilised transfer product "
+                                 "would lose the determinant", growth, kLogDetMaxGrowth);
+    if (overlaps(phi, (size_t)c->N * sizeof(double), out_dev, 2 * sizeof(double)))
+        return fail(HUB_ERR_ARG, "phi and output overlap");
+    if (hub_status d = check_device(c); d != HUB_OK) return d;
+    const size_t mb = (size_t)c->V * c->V * sizeof(cx<double>);
+    if (!c->ld_x) HIP_OR_FAIL(hipMalloc(&c->ld_x, mb));
+    if (!c->ld_y) HIP_OR_FAIL(hipMalloc(&c->ld_y, mb));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    cx<double>* X = static_cast<cx<double>*>(c->ld_x);
+    cx<double>* Y = static_cast<cx<double>*>(c->ld_y);
+    hipLaunchKernelGGL(k_identity, dim3(256), dim3(kThreads), 0, st, X, c->V);
+    hub_status s = launch_check("k_identity");
+    if (s != HUB_OK) return s;
+    // X <- E D_t X for t = 0 .. Nt-1: the V columns are the "slices" of one launch per slice
+    hub_ctx view = slab_view(c, c->V);
+    view.N = (long long)c->V * c->V;
+    view.path = HUB_PATH_FUSED;           // a slice of V <= 1152 sites always fits LDS: no split scratch
+    view.split_forced = false;
+    for (int t = 0; t < c->Nt; ++t) {
+        s = run_op<double>(&view, 1, SrcPhaseCol<double>{X, PhAngle<double>{phi + (size_t)t * c->V}},
+                           EpiStore<double>{Y}, CtlPlain{}, st);
+        if (s != HUB_OK) return s;
+        std::swap(X, Y);
+    }
+    hipLaunchKernelGGL(k_add_identity, dim3((c->V + kThreads - 1) / kThreads), dim3(kThreads), 0, st, X, c->V);
+    s = launch_check("k_add_identity");
+    if (s != HUB_OK) return s;
+    hipLaunchKernelGGL(k_lu_logdet, dim3(1), dim3(kLuThreads), 2 * c->V * sizeof(cx<double>), st, X, c->V, out_dev);
+    return launch_check("k_lu_logdet");
 }
 
 hub_status hub_action(hub_ctx* c, const void* chi, const void* x, int32_t nrhs, double* S_dev, void* stream) {

@@ -38,7 +38,7 @@ struct hub_ctx {
     int device = 0;
     int L = 0, Nt = 0, V = 0, nrhs_max = 0;
     long long N = 0;                 // V * Nt
-    double beta = 0, kappa = 0, delta = 0;
+    double beta = 0, kappa = 0, delta = 0, mu = 0;
     int path = HUB_PATH_FUSED;
     int form = HUB_FORM_EXP;
     bool specialized = true;         // use a compile-time-L kernel when one exists
@@ -86,4 +86,7 @@ struct hub_ctx {
     double* tr_E = nullptr;              // [2] device: boson energy, action
     double* tr_E_host = nullptr;         // [2] pinned mirror
     double* force_tmp = nullptr;         // [nrhs_max][N] doubles, per-rhs force before summation (hub_create)
+    // log det workspace (allocated on the first hub_log_det): two V x V complex128 matrices
+    void* ld_x = nullptr;
+    void* ld_y = nullptr;
 };

@@ -467,6 +467,33 @@ struct EpiForceSlab {            // g_t = -2 B_{t0+t+1} Im(e^{i phi_t} x_t conj(
     }
 };
 
+// ----------------------------------------------------------------------------- Sec. 3 weight
+// The transfer-matrix product E D_{Nt-1} ... E D_0 applied to the V columns of a V x V matrix:
+// one launch per slice, column j of the matrix is "slice" j of the launch.
+template <typename R>
+struct SrcPhaseCol {             // e^{i phi_t} X[:, j]   (ph points at slice t of phi)
+    using Pre = PrePh<R, PhAngle<R>>;
+    const cx<R>* X;
+    PhAngle<R> ph;
+    __device__ int slice(int j, int) const { return j; }
+    __device__ Pre fetch(int, int j, int i, const OpTab<R>& T) const {
+        return {X[(long long)j * T.V + i], ph.fetch(i)};
+    }
+    __device__ cx<R> make(const Pre& a, const Scal&) const { return cmul(a.v, ph.value(a.ph)); }
+};
+
+struct NoPre {};
+
+template <typename R>
+struct EpiStore {                // out = w
+    using Pre = NoPre;
+    cx<R>* out;
+    __device__ Pre fetch(int, int, int, const OpTab<R>&) const { return {}; }
+    __device__ void store(int rhs, int t, int i, cx<R> w, const Pre&, const OpTab<R>& T, const Scal&, double&) const {
+        out[rhs * T.N + (long long)t * T.V + i] = w;
+    }
+};
+
 // fetch + store in one call (kernels that do not prefetch)
 template <typename R, class Epi>
 __device__ __forceinline__ void epi_apply(const Epi& epi, int rhs, int t, int i, cx<R> w, const OpTab<R>& T,
@@ -1697,6 +1724,103 @@ k_sum_rhs(const double* __restrict__ parts, double* __restrict__ g, long long n,
         double s = parts[i];
         for (int r = 1; r < nrhs; ++r) s += parts[r * n + i];
         g[i] = s;
+    }
+}
+
+// X = 1 (V x V, column-major)
+__global__ void __launch_bounds__(kThreads)
+k_identity(cx<double>* __restrict__ X, int V) {
+    const long long n = (long long)V * V;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        X[e] = {(e / V == e % V) ? 1.0 : 0.0, 0.0};
+}
+
+// X += 1
+__global__ void __launch_bounds__(kThreads)
+k_add_identity(cx<double>* __restrict__ X, int V) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < V; j += gridDim.x * blockDim.x)
+        X[(long long)j * V + j].re += 1.0;
+}
+
+// log|det A| and arg det A of a V x V complex matrix (column-major: A[j * V + i] is row i of
+// column j) by LU with partial pivoting (largest |a_ik|, ties to the lowest row) in one
+// workgroup of kLuThreads; A is overwritten.  out[0] = log|det A| (-inf when a pivot column
+// is zero), out[1] = arg det A reduced to (-pi, pi].  Every sum has a fixed order.
+constexpr int kLuThreads = 1024;
+
+__global__ void __launch_bounds__(kLuThreads)
+k_lu_logdet(cx<double>* __restrict__ A, int V, double* __restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<double>* lcol = reinterpret_cast<cx<double>*>(smem);     // multipliers of column k
+    cx<double>* urow = lcol + V;                               // row k right of the pivot
+    __shared__ double wbest[kLuThreads / 64];
+    __shared__ int widx[kLuThreads / 64];
+    __shared__ int piv;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double lsum = 0.0, asum = 0.0;                              // thread 0's accumulators
+    bool singular = false;
+    for (int k = 0; k < V; ++k) {
+        double best = -1.0;
+        int bi = V;
+        for (int i = k + tid; i < V; i += kLuThreads) {
+            const cx<double> a = A[(long long)k * V + i];
+            const double m = a.re * a.re + a.im * a.im;
+            if (m > best) { best = m; bi = i; }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (lane == 0) { wbest[wave] = best; widx[wave] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = wbest[0];
+            int p = widx[0];
+            for (int w = 1; w < kLuThreads / 64; ++w)
+                if (wbest[w] > b || (wbest[w] == b && widx[w] < p)) { b = wbest[w]; p = widx[w]; }
+            piv = (b > 0.0) ? p : -1;
+        }
+        __syncthreads();
+        const int p = piv;
+        if (p < 0) { singular = true; break; }          // uniform: every thread read the same piv
+        if (p != k) {
+            for (int j = tid; j < V; j += kLuThreads) {
+                const long long c = (long long)j * V;
+                const cx<double> t = A[c + k];
+                A[c + k] = A[c + p];
+                A[c + p] = t;
+            }
+        }
+        __syncthreads();
+        const cx<double> akk = A[(long long)k * V + k];
+        if (tid == 0) {
+            lsum += 0.5 * log(akk.re * akk.re + akk.im * akk.im);
+            asum = remainder(asum + atan2(akk.im, akk.re) + (p != k ? 3.14159265358979323846 : 0.0),
+                             6.28318530717958647692);
+        }
+        const double inv = 1.0 / (akk.re * akk.re + akk.im * akk.im);
+        for (int i = k + 1 + tid; i < V; i += kLuThreads) {
+            const cx<double> a = A[(long long)k * V + i];
+            lcol[i] = {(a.re * akk.re + a.im * akk.im) * inv, (a.im * akk.re - a.re * akk.im) * inv};   // a / akk
+        }
+        for (int j = k + 1 + tid; j < V; j += kLuThreads) urow[j] = A[(long long)j * V + k];
+        __syncthreads();
+        const int m = V - k - 1;
+        const long long tot = (long long)m * m;
+        for (long long e = tid; e < tot; e += kLuThreads) {
+            const int j = k + 1 + (int)(e / m), i = k + 1 + (int)(e % m);
+            const cx<double> l = lcol[i], u = urow[j];
+            cx<double>& a = A[(long long)j * V + i];
+            a.re -= l.re * u.re - l.im * u.im;
+            a.im -= l.re * u.im + l.im * u.re;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[0] = singular ? -__builtin_huge_val() : lsum;
+        out[1] = singular ? 0.0 : asum;
     }
 }
 

@@ -436,3 +436,43 @@ def test_chemical_potential_routes_agree():
     a = np.vdot(u, op.apply_M(phi, v))
     b = np.vdot(op.apply_Mdag(phi, u), v)
     assert abs(a - b) < 1e-12 * abs(a)
+
+
+# ----------------------------------------------------------------------------- Sec. 3 weight
+def test_oracle_log_det_routes():
+    """The transfer-product log det equals the dense slogdet of M (any field, mu = 0 and mu != 0)
+    and the free closed form with a chemical potential; the sign phase is zero at mu = 0 and
+    at phi = 0, nonzero on a random field at mu != 0 (Sec. 3: the sign problem)."""
+    w = TINY
+    phi, _ = draw_inputs(w)
+    for mu in (0.0, 0.4, -0.9):
+        op = O.HubbardOperator(w.L, w.Nt, w.beta, mu=mu)
+        s, ld = np.linalg.slogdet(op.dense_M(phi))
+        l2, a2 = O.log_det(op, phi)
+        assert abs(ld - l2) < 1e-11 * abs(ld) and abs(np.exp(1j * a2) - s) < 1e-11
+        l0, a0 = O.log_det(op, np.zeros_like(phi))
+        a = np.abs(CF.f_of_k(w.L)).ravel()
+        ref = np.sum(np.log1p(np.exp(w.beta * (mu + a)))) + np.sum(np.log1p(np.exp(w.beta * (mu - a))))
+        assert abs(l0 - ref) < 1e-11 * abs(ref) and abs(a0) < 1e-12
+    opp = O.HubbardOperator(w.L, w.Nt, w.beta, mu=0.4)
+    opm = O.HubbardOperator(w.L, w.Nt, w.beta, mu=-0.4)
+    op0 = O.HubbardOperator(w.L, w.Nt, w.beta)
+    assert abs(O.sign_phase(op0, op0, phi)) == 0.0
+    assert abs(O.sign_phase(opp, opm, np.zeros_like(phi))) < 1e-12
+    th = O.sign_phase(opp, opm, phi)
+    Mp, Mm = opp.dense_M(phi), opm.dense_M(phi)
+    s, _ = np.linalg.slogdet(Mp @ Mm.conj().T)
+    assert abs(np.exp(1j * th) - s) < 1e-10 and abs(th) > 1e-6
+
+
+def test_reweighting_identity():
+    """<O>_p = <O e^{i theta}>_|p| / <e^{i theta}>_|p|: for samples drawn with weights |p_i| of a
+    finite set, the ratio equals the exact sum over the set with the complex weights p_i."""
+    rng = np.random.default_rng(4)
+    n = 6
+    p = rng.uniform(0.1, 1.0, n) * np.exp(1j * rng.uniform(-2.5, 2.5, n))
+    obs = rng.normal(size=n)
+    exact = np.sum(obs * p) / np.sum(p)
+    draws = rng.choice(n, size=400000, p=np.abs(p) / np.abs(p).sum())
+    est = O.reweight(obs[draws], np.angle(p)[draws])
+    assert abs(est - exact) < 0.02 * abs(exact)
