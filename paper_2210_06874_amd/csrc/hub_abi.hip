@@ -14,16 +14,10 @@ using namespace hub;
 
 namespace {
 
-#ifndef HUB_THREADS_51
-#define HUB_THREADS_51 512
-#endif
-constexpr int kThreads51 = HUB_THREADS_51;   // workgroup size of the L = 51 kernels
+constexpr int kThreads51 = 512;     // workgroup size of the L = 51 kernels
 // the minimum-norm choice of the Omelyan-Mryglod-Folk second-order integrator
 constexpr double kOmelyanLambda = 0.1931833275037836;
-#ifndef HUB_HALF_BELOW
-#define HUB_HALF_BELOW 256
-#endif
-constexpr int kHalfBelow = HUB_HALF_BELOW;       // two workgroups per slice below this many slices
+constexpr int kHalfBelow = 256;     // two workgroups per slice below this many slices
 
 thread_local char g_err[512] = "";
 
@@ -80,23 +74,16 @@ constexpr double kLogDetMaxGrowth = 29.0;
 
 // Split-path tiles: about this many complex entries per row block and per column block
 // (both sublattices), rounded to an even division of L.
-#ifndef HUB_SPLIT_ROW_ELEMS
-#define HUB_SPLIT_ROW_ELEMS 2048
-#endif
-#ifndef HUB_SPLIT_COL_ELEMS
-#define HUB_SPLIT_COL_ELEMS 2048
-#endif
-#ifndef HUB_THREADS_SPLIT
-#define HUB_THREADS_SPLIT 256
-#endif
-constexpr int kThreadsSplit = HUB_THREADS_SPLIT;   // workgroup size of the compile-time split kernels
+constexpr int kSplitRowElems = 2048;
+constexpr int kSplitColElems = 2048;
+constexpr int kThreadsSplit = 256;  // workgroup size of the compile-time split kernels
 
 constexpr SplitGeom split_geom(int L) {
     SplitGeom g{};
-    int rb0 = std::max(1, std::min(L, HUB_SPLIT_ROW_ELEMS / L));
+    int rb0 = std::max(1, std::min(L, kSplitRowElems / L));
     g.nrb = (L + rb0 - 1) / rb0;
     g.rb = (L + g.nrb - 1) / g.nrb;
-    int cb0 = std::max(1, std::min(L, HUB_SPLIT_COL_ELEMS / L));
+    int cb0 = std::max(1, std::min(L, kSplitColElems / L));
     g.ncb = (L + cb0 - 1) / cb0;
     g.cb = (L + g.ncb - 1) / g.ncb;
     return g;
@@ -141,19 +128,10 @@ enum class OpKind { Generic, Whole51, Half51, Split, Linear, Sub102 };
 // per compute unit, so the waves per CU are the workgroup's own: twelve (three per SIMD)
 // hide more latency than eight, at the price of a few register spills outside the
 // butterfly loops; sixteen spill more.
-#ifndef HUB_THREADS_SUB
-#define HUB_THREADS_SUB 768
-#endif
-constexpr int kThreadsSub = HUB_THREADS_SUB;
+constexpr int kThreadsSub = 768;
 
-#ifndef HUB_LIN_BATCH
-#define HUB_LIN_BATCH 3
-#endif
-#ifndef HUB_LIN_TARGET
-#define HUB_LIN_TARGET 256
-#endif
-constexpr int kLinBatch = HUB_LIN_BATCH;     // sites per thread with loads in flight together
-constexpr int kLinTarget = HUB_LIN_TARGET;   // fewest workgroups per launch worth splitting slices for
+constexpr int kLinBatch = 3;        // sites per thread with loads in flight together
+constexpr int kLinTarget = 256;     // fewest workgroups per launch worth splitting slices for
 
 // Linear form: chunks per slice.  Enough workgroups to fill the chip (kLinTarget), and
 // chunks small enough for one batch of loads per thread, while the reduction slots per

@@ -319,6 +319,58 @@ __device__ __forceinline__ void small_dft_ct(cx<R>* x) {
     }
 }
 
+// One odd r-point DFT (real-coefficient split, constant coefficients) shared by a lane pair:
+// half q = 0 forms the real part of every output, q = 1 the imaginary part.  Forward, with
+// e_j = x_j + x_{r-j}, o_j = x_j - x_{r-j}, A_k = x_0 + sum_j cos(2 pi jk/r) e_j and
+// B_k = sum_j sin(2 pi jk/r) o_j:  X_k = A_k - i B_k and X_{r-k} = A_k + i B_k, so
+//     Re X_k = Re A_k + Im B_k,  Im X_k = Im A_k - Re B_k   (signs of B swap for X_{r-k}
+// and for the inverse).  Lane q needs the q-th component of A and the other one of B: the
+// whole butterfly's arithmetic split in two halves with nothing computed twice but the pair
+// sums.  y receives the lane's component of X_0 .. X_{r-1}.
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void small_dft_pair(const cx<R>* x, int q, R* y) {
+    constexpr DftConst<RAD> K{};
+    constexpr int H = (RAD - 1) / 2;
+    // values are formed first and selected after, so that no select picks between two
+    // addresses of x (which would keep x in scratch memory instead of registers)
+    R e[H + 1], o[H + 1];
+    const cx<R> z = x[0];
+    const R x0 = q ? z.im : z.re;
+    R s0 = x0;
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        const cx<R> a = x[j], b = x[RAD - j];
+        const R sr = a.re + b.re, si = a.im + b.im, dr = a.re - b.re, di = a.im - b.im;
+        e[j] = q ? si : sr;
+        o[j] = q ? dr : di;
+        s0 += e[j];
+    }
+    y[0] = s0;
+    // forward: lane 0 adds B to X_k, lane 1 subtracts it; the inverse the other way round
+    const R sg = ((q == 0) != INV) ? (R)1 : (R)-1;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        R A = x0, B = (R)0;
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const int m = (j * k) % RAD;
+            A = fmar((R)K.c[m], e[j], A);
+            B = fmar((R)K.s[m], o[j], B);
+        }
+        y[k] = fmar(sg, B, A);
+        y[RAD - k] = fmar(-sg, B, A);
+    }
+}
+
+// Stages whose radix is odd and >= 5 with no twiddle factors (the last forward stage, the
+// first inverse one) and whose butterflies fill at most half of the workgroup's lanes share
+// each butterfly between a lane pair (small_dft_pair): twice the tasks at about half the
+// arithmetic each, so that the stage keeps two waves on a SIMD where it kept one (a single
+// wave per SIMD cannot hide the latency of its dependent FMAs).  Stages with more butterflies
+// than that already keep two waves per SIMD and keep one lane per butterfly.  FP32 only: in
+// FP64 each lane of a pair reads twice the bytes through LDS and the pairs measured no faster.
+constexpr bool kPairOddStages = true;
+
 // Stage Q of the row (COLS = false) or column (COLS = true) transforms of NS
 // sublattice tiles [NS][L][L] in LDS (a whole slice when NS = 2).  Row tasks run along a line (consecutive threads read
 // consecutive positions); column tasks run across lines (consecutive threads read
@@ -329,6 +381,29 @@ __device__ __forceinline__ void ct_stage(cx<R>* __restrict__ buf, const cx<R>* _
     constexpr int RAD = P.radix[Q], LQ = P.len[Q], M = LQ / RAD, PER = L / RAD;
     constexpr int NL = NS * L, NTASK = NL * PER, TWS = L / LQ;
     constexpr int ST = COLS ? M * L : M;
+    if constexpr (kPairOddStages && sizeof(R) == sizeof(float) && RAD >= 5 && M == 1 && 2 * NTASK <= NT) {
+        for (int t2 = threadIdx.x; t2 < 2 * NTASK; t2 += NT) {
+            const int task = t2 >> 1, q = t2 & 1;
+            int base;
+            if constexpr (COLS) {
+                const int b = task / NL, line = task - b * NL;
+                const int s = line >= L ? 1 : 0;
+                base = s * L * L + (line - s * L) + b * LQ * L;
+            } else {
+                const int line = task / PER, b = task - line * PER;
+                base = line * L + b * LQ;
+            }
+            cx<R> x[RAD];
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) x[i] = buf[base + i * ST];
+            R y[RAD];
+            small_dft_pair<R, RAD, INV>(x, q, y);
+            R* comp = reinterpret_cast<R*>(buf) + q;
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) comp[2 * (base + i * ST)] = y[i];
+        }
+        return;
+    }
     for (int task = threadIdx.x; task < NTASK; task += NT) {
         int line, j;
         if constexpr (COLS) {

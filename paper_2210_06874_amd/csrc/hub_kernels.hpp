@@ -94,6 +94,63 @@ __device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], int 
     __syncthreads();
 }
 
+// The first partial of each of K arrays that this thread sums (slot threadIdx.x, clamped into
+// range), loaded ahead of a kernel's other global loads: the memory counter is waited on in
+// issue order, so partials loaded after the prefetch of the operands would make every wave wait
+// for all of those before it could form the CG scalars.
+template <int K>
+struct PartialsPre {
+    double v[K];
+    double tol2;                 // and the right-hand side's state, from the scalars
+    int done, nonfinite, iters;
+};
+
+template <int K>
+__device__ __forceinline__ PartialsPre<K> prefetch_partials(const double* const (&p)[K], int n,
+                                                            const CgScalars& s) {
+    PartialsPre<K> r;
+    const int j = min((int)threadIdx.x, n - 1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.v[k] = p[k][j];
+    r.tol2 = s.tol2;
+    r.done = s.done;
+    r.nonfinite = s.nonfinite;
+    r.iters = s.iters;
+    return r;
+}
+
+// sum_partials_k with each thread's first partial already loaded (same order, same sums).
+template <int K>
+__device__ __forceinline__ void sum_partials_pre(const double* const (&p)[K], int n, const PartialsPre<K>& pre,
+                                                 double* lds, double (&out)[K]) {
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = (int)threadIdx.x < n ? pre.v[k] : 0.0;
+    for (int j = threadIdx.x + blockDim.x; j < n; j += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += p[k][j];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[wave * K + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[w * K + k];
+        out[k] = s;
+    }
+    __syncthreads();
+}
+
+struct NoCtlPre {};
+
 // What an operator kernel's block learns before it starts: whether it works at all,
 // and the CG step scalars.
 struct Scal {
@@ -594,8 +651,13 @@ struct FinStore {                // out[0] = sum over right-hand sides (in order
 // An operator kernel asks its control policy, before anything else, whether the block
 // works and with which CG scalars (begin), and hands it the block's reduction value at
 // the end (end).  begin() and end() are called by every thread of the block.
+// A kernel that prefetches calls prefetch(rhs) before its own loads and hands the result to
+// begin(); the others call begin(rhs, slot, lds).
 struct CtlPlain {                // operators and force: always work, nothing reduced
     static constexpr bool kEnd = false;
+    using Pre = NoCtlPre;
+    __device__ Pre prefetch(int) const { return {}; }
+    __device__ Scal begin(int, int, double*, const Pre&) const { return {1, 0.0, 0.0}; }
     __device__ Scal begin(int, int, double*) const { return {1, 0.0, 0.0}; }
     __device__ void end(double, int, int, const Scal&, double*) const {}
     CtlPlain with_slots(int) const { return *this; }
@@ -605,7 +667,10 @@ struct CtlGate {                 // gate from the CG scalars, nothing reduced
     static constexpr bool kEnd = false;
     const CgScalars* sc;
     int gate;
+    using Pre = NoCtlPre;
+    __device__ Pre prefetch(int) const { return {}; }
     __device__ Scal begin(int rhs, int, double*) const { return {gate_open(sc, gate, rhs) ? 1 : 0, 0.0, 0.0}; }
+    __device__ Scal begin(int rhs, int slot, double* lds, const Pre&) const { return begin(rhs, slot, lds); }
     __device__ void end(double, int, int, const Scal&, double*) const {}
     CtlGate with_slots(int) const { return *this; }
 };
@@ -617,7 +682,10 @@ struct CtlAtomic {               // gate from the CG scalars; last-block finaliz
     int gate;
     RedArgs ra;
     Fin fin;
+    using Pre = NoCtlPre;
+    __device__ Pre prefetch(int) const { return {}; }
     __device__ Scal begin(int rhs, int, double*) const { return {gate_open(sc, gate, rhs) ? 1 : 0, 0.0, 0.0}; }
+    __device__ Scal begin(int rhs, int slot, double* lds, const Pre&) const { return begin(rhs, slot, lds); }
     __device__ void end(double acc, int rhs, int slot, const Scal&, double* lds) const {
         reduce_and_finalize(acc, rhs, slot, ra, fin, lds);
     }
@@ -639,14 +707,20 @@ struct CtlSearch {
     double* tt_out;
     CgScalars* sc;
     int slots;
-    __device__ Scal begin(int rhs, int slot, double* lds) const {
+    using Pre = PartialsPre<2>;
+    __device__ Pre prefetch(int rhs) const {
+        const long long o = (long long)rhs * slots;
+        const double* const p[2] = {rr_i + o, rr_im1 + o};
+        return prefetch_partials<2>(p, slots, sc[rhs]);
+    }
+    __device__ Scal begin(int rhs, int slot, double* lds) const { return begin(rhs, slot, lds, prefetch(rhs)); }
+    __device__ Scal begin(int rhs, int slot, double* lds, const Pre& pre) const {
         const long long o = (long long)rhs * slots;
         const double* const p[2] = {rr_i + o, rr_im1 + o};
         double sum[2];
-        sum_partials_k<2>(p, slots, lds, sum);
+        sum_partials_pre<2>(p, slots, pre, lds, sum);
         const double a = sum[0], b = sum[1];
-        const CgScalars& s = sc[rhs];
-        int open = (!s.done && !s.nonfinite && a > s.tol2) ? 1 : 0;
+        int open = (!pre.done && !pre.nonfinite && a > pre.tol2) ? 1 : 0;
         const double beta = a / b;
         if (open && !isfinite(beta)) {
             open = 0;
@@ -672,21 +746,27 @@ struct CtlUpdate {
     double* rr_next;
     CgScalars* sc;
     int slots;
-    __device__ Scal begin(int rhs, int slot, double* lds) const {
+    using Pre = PartialsPre<3>;
+    __device__ Pre prefetch(int rhs) const {
+        const long long o = (long long)rhs * slots;
+        const double* const p[3] = {rr_i + o, rr_im1 + o, tt + o};
+        return prefetch_partials<3>(p, slots, sc[rhs]);
+    }
+    __device__ Scal begin(int rhs, int slot, double* lds) const { return begin(rhs, slot, lds, prefetch(rhs)); }
+    __device__ Scal begin(int rhs, int slot, double* lds, const Pre& pre) const {
         const long long o = (long long)rhs * slots;
         const double* const p[3] = {rr_i + o, rr_im1 + o, tt + o};
         double sum[3];
-        sum_partials_k<3>(p, slots, lds, sum);
+        sum_partials_pre<3>(p, slots, pre, lds, sum);
         const double a = sum[0], b = sum[1], c = sum[2];
-        const CgScalars& s = sc[rhs];
-        int open = (!s.done && !s.nonfinite && a > s.tol2) ? 1 : 0;
+        int open = (!pre.done && !pre.nonfinite && a > pre.tol2) ? 1 : 0;
         const double alpha = a / c, beta = a / b;
         if (open && (!(c > 0.0) || !isfinite(alpha) || !isfinite(beta))) {
             open = 0;
             if (slot == 0 && threadIdx.x == 0) sc[rhs].nonfinite = 1;
         }
         if (open && slot == 0 && threadIdx.x == 0) {
-            sc[rhs].iters += 1;
+            sc[rhs].iters = pre.iters + 1;
             sc[rhs].rr_last = a;
         }
         return {open, alpha, beta};
@@ -755,10 +835,11 @@ k_fused(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
 // Same layout with L known at compile time (NT threads per workgroup).  The first
 // row stage is fused into the source load and the last inverse row stage into the
 // epilogue, so the slice makes two fewer round trips through LDS.  Every global load
-// is issued before the first butterfly (source entries, E(k) values and, when they fit
-// the register budget, the epilogue operands; else those one stage before the
-// epilogue), and the part of the epilogue that does not depend on the transform
-// (early()) runs after the forward row stages, so its stores overlap the rest of it.
+// is issued ahead of its use: the source entries before anything else, E(k) and (when they
+// fit the register budget) the epilogue operands once the source has been consumed, else the
+// epilogue operands one stage before the epilogue; the part of the epilogue that does not
+// depend on the transform (early()) runs after the forward stages, so its stores overlap the
+// rest of it.
 //
 // HALF = true runs two workgroups per slice when there are fewer slices than compute
 // units: both transform the whole source slice forward (the 2 x 2 hopping exponential
@@ -799,46 +880,81 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     const int off = HALF ? h * LL : 0;                  // first site written
     const int slot = HALF ? 2 * t + h : t;
     const int tid = threadIdx.x;
-    // Every global load is issued before the block learns its CG scalars (the loads do
-    // not depend on them), so the scalar reduction overlaps the fetch.
+    static_assert(NT >= L, "one root of unity per thread");
+    // Every global load is issued before the block learns its CG scalars (the loads do not
+    // depend on them), so the scalar reduction overlaps the fetch.
+    //
+    // FP32 (kDefer): the loads are issued in the order their data is needed and
+    // unconditionally (indices clamped into range, the surplus lanes' values unused): the
+    // memory counter is waited on in issue order, so a load under a branch, or one needed
+    // early but issued late, would make the wave wait for every load before it.  The CG
+    // partials and the roots come first; E(k) and the early epilogue operands only once the
+    // source has been consumed (issued with it they would share its bandwidth and delay the
+    // first stage; from there they arrive during the forward transform).
+    // FP64: source, E(k) and epilogue operands together at the start, the roots when the block
+    // opens; its first stage is long (the FP64 phases), and the FP32 order measured slower.
+    constexpr bool kDefer = sizeof(R) == sizeof(float);
+    typename Ctl::Pre cpre{};
+    cx<R> root_v{};
+    const int rt = tid < L ? tid : L - 1;
+    if constexpr (kDefer) {
+        cpre = ctl.prefetch(rhs);
+        root_v = T.roots[rt];
+        __builtin_amdgcn_sched_barrier(0);    // keep the issue order: the scheduler may not mix the groups
+    }
     const int ts = src.slice(t, T.Nt);
     typename Src::Pre pre[ROUNDS0][R0];
 #pragma unroll
     for (int rd = 0; rd < ROUNDS0; ++rd) {
         const int task = tid + rd * NT;
-        if (task < NT0) {
-            const int line = task / M0, np = task - line * M0;
+        if (kDefer || task < NT0) {
+            const int tc = kDefer ? min(task, NT0 - 1) : task;
+            const int line = tc / M0, np = tc - line * M0;
 #pragma unroll
             for (int i = 0; i < R0; ++i) pre[rd][i] = src.fetch(rhs, ts, line * L + np + i * M0, T);
         }
     }
-    R ec[ROUNDSE][3];
-#pragma unroll
-    for (int rd = 0; rd < ROUNDSE; ++rd) {
-        const int p = tid + rd * NT;
-        if (p < LL) {
-            ec[rd][0] = T.etab[4 * p];
-            ec[rd][1] = T.etab[4 * p + 1];
-            ec[rd][2] = T.etab[4 * p + 2];
-        }
-    }
-    // epilogue operands, issued with the source (they do not depend on the transform)
+    if constexpr (kDefer) __builtin_amdgcn_sched_barrier(0);
     typename Epi::Pre ep[kPreEpi ? ROUNDSO : 1][kPreEpi ? R0 : 1];
-    if constexpr (kPreEarly) {
+    R ec[ROUNDSE][3];
+    auto fetch_e = [&]() {
 #pragma unroll
-        for (int rd = 0; rd < ROUNDSO; ++rd) {
-            const int task = tid + rd * NT;
-            if (task < NTE) {
-                const int line = task / M0, np = task - line * M0;
-#pragma unroll
-                for (int i = 0; i < R0; ++i) ep[rd][i] = epi.fetch(rhs, t, off + line * L + np + i * M0, T);
+        for (int rd = 0; rd < ROUNDSE; ++rd) {
+            const int p = tid + rd * NT;
+            if (kDefer || p < LL) {
+                const int pc = kDefer ? min(p, LL - 1) : p;
+                ec[rd][0] = T.etab[4 * pc];
+                ec[rd][1] = T.etab[4 * pc + 1];
+                ec[rd][2] = T.etab[4 * pc + 2];
             }
         }
+    };
+    auto fetch_ep = [&]() {
+        if constexpr (kPreEarly) {
+#pragma unroll
+            for (int rd = 0; rd < ROUNDSO; ++rd) {
+                const int task = tid + rd * NT;
+                if (kDefer || task < NTE) {
+                    const int tc = kDefer ? min(task, NTE - 1) : task;
+                    const int line = tc / M0, np = tc - line * M0;
+#pragma unroll
+                    for (int i = 0; i < R0; ++i) ep[rd][i] = epi.fetch(rhs, t, off + line * L + np + i * M0, T);
+                }
+            }
+        }
+    };
+    if constexpr (!kDefer) {
+        fetch_e();
+        fetch_ep();
     }
-    const Scal sc = ctl.begin(rhs, slot, red_lds);
+    const Scal sc = kDefer ? ctl.begin(rhs, slot, red_lds, cpre) : ctl.begin(rhs, slot, red_lds);
     double acc = 0.0;
     if (sc.open) {
-        for (int i = tid; i < L; i += NT) roots[i] = T.roots[i];
+        if constexpr (kDefer) {
+            roots[rt] = root_v;
+        } else {
+            for (int i = tid; i < L; i += NT) roots[i] = T.roots[i];
+        }
         __syncthreads();
         // row stage 0 (natural-order input) from the prefetched entries
 #pragma unroll
@@ -859,20 +975,31 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
                 for (int i = 0; i < R0; ++i) buf[base + i * M0] = x[i];
             }
         }
+        if constexpr (kDefer) {
+            fetch_e();          // E(k) first: the mix needs it before the epilogue does
+            fetch_ep();
+        }
         __syncthreads();
-        ct_forward<R, L, 1, P.nst, false, NT>(buf, roots);
-        if constexpr (kPreEarly) {
+        // the early epilogue after the row stages, or in FP32 after the column stages too (its
+        // operands were issued later there)
+        auto do_early = [&]() {
+            if constexpr (kPreEarly) {
 #pragma unroll
-            for (int rd = 0; rd < ROUNDSO; ++rd) {
-                const int task = tid + rd * NT;
-                if (task < NTE) {
-                    const int line = task / M0, np = task - line * M0;
+                for (int rd = 0; rd < ROUNDSO; ++rd) {
+                    const int task = tid + rd * NT;
+                    if (task < NTE) {
+                        const int line = task / M0, np = task - line * M0;
 #pragma unroll
-                    for (int i = 0; i < R0; ++i) epi_early<R>(epi, rhs, t, off + line * L + np + i * M0, ep[rd][i], T, sc);
+                        for (int i = 0; i < R0; ++i)
+                            epi_early<R>(epi, rhs, t, off + line * L + np + i * M0, ep[rd][i], T, sc);
+                    }
                 }
             }
-        }
+        };
+        ct_forward<R, L, 1, P.nst, false, NT>(buf, roots);
+        if constexpr (!kDefer) do_early();
         ct_forward<R, L, 0, P.nst, true, NT>(buf, roots);
+        if constexpr (kDefer) do_early();
         // E(k): A' = c A + sf B,  B' = conj(sf) A + c B
 #pragma unroll
         for (int rd = 0; rd < ROUNDSE; ++rd) {
@@ -959,24 +1086,30 @@ k_fused_sub(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     const int u = xcd_linear(blockIdx.x, gridDim.x);
     const int rhs = u / T.Nt, t = u - rhs * T.Nt;
     const int tid = threadIdx.x;
+    static_assert(NT >= L, "one root of unity per thread");
+    // loads in the order their data is needed, unconditionally (indices clamped into range):
+    // the memory counter is waited on in issue order (see k_fused_ct)
+    const typename Ctl::Pre cpre = ctl.prefetch(rhs);
+    const int rt = tid < L ? tid : L - 1;
+    const cx<R> root_v = T.roots[rt];
+    __builtin_amdgcn_sched_barrier(0);    // keep the issue order (see k_fused_ct)
     const int ts = src.slice(t, T.Nt);
     typename Src::Pre pre[ROUNDS][R0];
     auto fetch_sub = [&](int s) {
 #pragma unroll
         for (int rd = 0; rd < ROUNDS; ++rd) {
-            const int task = tid + rd * NT;
-            if (task < NTS) {
-                const int line = task / M0, np = task - line * M0;
+            const int task = min(tid + rd * NT, NTS - 1);
+            const int line = task / M0, np = task - line * M0;
 #pragma unroll
-                for (int i = 0; i < R0; ++i) pre[rd][i] = src.fetch(rhs, ts, s * LL + line * L + np + i * M0, T);
-            }
+            for (int i = 0; i < R0; ++i) pre[rd][i] = src.fetch(rhs, ts, s * LL + line * L + np + i * M0, T);
         }
     };
     fetch_sub(0);
-    const Scal sc = ctl.begin(rhs, t, red_lds);
+    __builtin_amdgcn_sched_barrier(0);
+    const Scal sc = ctl.begin(rhs, t, red_lds, cpre);
     double acc = 0.0;
     if (sc.open) {
-        for (int i = tid; i < L; i += NT) roots[i] = T.roots[i];
+        roots[rt] = root_v;
         cx<R> ahat[NP];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -1361,10 +1494,7 @@ k_split_rows_inv_ct(const OpTab<R> T, const cx<R>* __restrict__ W, const Epi epi
 // (y over the three neighbours on the other sublattice, B_0 = -1).  Every output is one
 // diagonal term, one time hop and three equal-time hops, so the kernel streams its
 // vectors once from HBM; the neighbour entries are re-read from the caches.
-#ifndef HUB_LIN_THREADS
-#define HUB_LIN_THREADS 512
-#endif
-constexpr int kLinThreads = HUB_LIN_THREADS;
+constexpr int kLinThreads = 512;
 
 template <typename R>
 struct LinTab {
