@@ -246,22 +246,30 @@ def stress_leg(dev, steps: int) -> dict:
     pw, cw = draw_weak_field(w, nrhs=w.nrhs)
     Pw, Cw = torch.from_numpy(pw).to(dev), torch.from_numpy(cw).to(dev)
     n_it = 50 * max(1, steps)
-    hub.cg_solve(Pw, Cw, tol=1e-10, prec="mixed", max_iter=50, raise_on_error=False)   # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = hub.cg_solve(Pw, Cw, tol=1e-10, prec="mixed", max_iter=n_it, raise_on_error=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    it = max(res.iters)
+    cg = {}
+    for mode in ("persistent", "two_kernel"):
+        hub.set_cg_launch(persistent=(mode == "persistent"))
+        hub.cg_solve(Pw, Cw, tol=1e-10, prec="mixed", max_iter=50, raise_on_error=False)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = hub.cg_solve(Pw, Cw, tol=1e-10, prec="mixed", max_iter=n_it, raise_on_error=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        it = max(res.iters)
+        cg[mode] = {"us_per_iteration": dt / it * 1e6, "iterations": it,
+                    "GBs": 96.0 * w.N * w.nrhs * it / dt / 1e9, "persistent_launches": res.persistent_launches}
+    hub.set_cg_launch(persistent=False)
     return {"workload": f"{w.name}: L={w.L} Nt={w.Nt} beta={w.beta} U={w.U}, {w.nrhs} right-hand sides per launch",
             "apply_M_c64_us": t32 * 1e6, "apply_M_c64_GBs": alg32 / t32 / 1e9,
             "apply_M_c64_hbm_frac": alg32 / t32 / 1e9 / HBM_PEAK_GBS,
             "apply_M_us": t64 * 1e6, "apply_M_GBs": alg64 / t64 / 1e9,
             "apply_M_hbm_frac": alg64 / t64 / 1e9 / HBM_PEAK_GBS,
-            "cg_mixed_us_per_iteration": dt / it * 1e6, "cg_iterations": it,
-            "cg_GBs": 96.0 * w.N * w.nrhs * it / dt / 1e9,
-            "timing": "operators: HIP graphs, events on their stream; CG: wall time of one solve "
-                      "(includes its reliable updates)"}
+            "cg_mixed_us_per_iteration": cg["two_kernel"]["us_per_iteration"],
+            "cg_iterations": cg["two_kernel"]["iterations"], "cg_GBs": cg["two_kernel"]["GBs"],
+            "cg_mixed_by_launch": cg,
+            "timing": "operators: HIP graphs, events on their stream; CG: wall time of one solve of "
+                      f"{n_it} iterations (includes its reliable updates), persistent launch and two "
+                      "launches per iteration"}
 
 
 def main() -> int:

@@ -121,6 +121,8 @@ typedef struct {
     int32_t reliable_updates;   /* FP64 residual recomputations                               */
     double true_rel_res;        /* ||chi - A x|| / ||chi|| in FP64 at exit                    */
     double recursive_rel_res;   /* the iterated residual's ||r|| / ||chi|| at exit            */
+    int32_t persistent_launches;/* persistent launches of the solve (hub_set_cg_launch), the same
+                                   in every entry; 0: two launches per iteration                 */
 } hub_cg_info;
 
 /* Create a context on the current HIP device: for HUB_FORM_EXP builds the momentum-space
@@ -276,6 +278,18 @@ hub_status hub_trajectory(hub_ctx* ctx, double* phi, const double* pi0, const vo
  * HUB_ERR_ARG; HUB_FORM_EXP only.  The first call allocates two V x V complex128 matrices in the
  * context.  Stream-ordered, no synchronisation. */
 hub_status hub_log_det(hub_ctx* ctx, const double* phi, double* out_dev, void* stream);
+
+/* CG launch policy of a context.  persistent = 1: the FP32 iterations of a mixed solve with the
+ * one-sublattice-at-a-time kernel (exponential form, L = 102) run as one cooperative launch per
+ * block of iterations (all right-hand sides in one launch; every workgroup loops over
+ * (right-hand side, slice) items, with grid barriers between the M^dag and M phases), provided
+ * the device holds the whole grid at once, else as two launches per iteration; the result is the
+ * same bit for bit.  persistent = 0 (the default, measured faster on MI355X): always two
+ * launches per iteration.
+ * barrier_spin_limit > 0 bounds every wait at a grid barrier to that many polls (0 restores the
+ * default, 2^24 polls, seconds); a wait that runs out makes every workgroup leave the launch and
+ * hub_cg_solve return HUB_ERR_DEVICE with x undefined. */
+hub_status hub_set_cg_launch(hub_ctx* ctx, int32_t persistent, int64_t barrier_spin_limit);
 
 /* Report the kernel path the context uses (hub_path value, never AUTO) and the
  * LDS bytes per workgroup of its operator kernel (HUB_FORM_LINEAR: FUSED and 0, one

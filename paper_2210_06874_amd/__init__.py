@@ -46,6 +46,7 @@ class CgResult:
     true_rel_res: list
     recursive_rel_res: list
     history: list | None = None     # per rhs: true relative residual after each reliable update
+    persistent_launches: int = 0    # persistent CG launches of the solve (0: two per iteration)
 
     @property
     def converged(self) -> bool:
@@ -256,7 +257,13 @@ class Hubbard:
                        [i.true_rel_res for i in info], [i.recursive_rel_res for i in info])
         if hist is not None:
             res.history = [hist[r, :min(info[r].reliable_updates, hist.shape[1])].copy() for r in range(nrhs)]
+        res.persistent_launches = info[0].persistent_launches
         return res
+
+    def set_cg_launch(self, persistent: bool = False, barrier_spin_limit: int = 0) -> None:
+        """hub_set_cg_launch: persistent CG launches where they apply, or two launches per iteration
+        (the default); barrier_spin_limit > 0 bounds each grid-barrier wait (polls)."""
+        _lib.check(self.lib.hub_set_cg_launch(self._h, 1 if persistent else 0, int(barrier_spin_limit)))
 
     def force(self, phi, x, out=None):
         """dS/dphi (float64 [Nt, V]) of S = chi^dag (M M^dag)^{-1} chi from the solutions x."""

@@ -31,7 +31,8 @@ class HubCgOpts(ctypes.Structure):
 
 class HubCgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("reliable_updates", ctypes.c_int32),
-                ("true_rel_res", ctypes.c_double), ("recursive_rel_res", ctypes.c_double)]
+                ("true_rel_res", ctypes.c_double), ("recursive_rel_res", ctypes.c_double),
+                ("persistent_launches", ctypes.c_int32)]
 
 
 class HubTrajOpts(ctypes.Structure):
@@ -68,6 +69,7 @@ SIGNATURES = {
     "hub_trajectory": (_P, _P, _P, _P, _I, ctypes.c_double, ctypes.POINTER(HubTrajOpts),
                        ctypes.POINTER(HubTrajInfo), _P),
     "hub_query": (_P, ctypes.POINTER(_I), ctypes.POINTER(_I)),
+    "hub_set_cg_launch": (_P, _I, ctypes.c_int64),
     "hub_last_error": (),
 }
 

@@ -419,7 +419,61 @@ hub_status ensure_cg_workspace(hub_ctx* c) {
         HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void**>(&c->scal_host), (size_t)c->nrhs_max * sizeof(CgScalars),
                                   hipHostMallocDefault));
     if (!c->cg_event) HIP_OR_FAIL(hipEventCreateWithFlags(&c->cg_event, hipEventDisableTiming));
+    if (!c->persist_bar) HIP_OR_FAIL(hipMalloc(reinterpret_cast<void**>(&c->persist_bar), 4 * sizeof(unsigned)));
+    if (!c->persist_flag_host)
+        HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void**>(&c->persist_flag_host), 4 * sizeof(unsigned),
+                                  hipHostMallocDefault));
     c->cg_ready = true;
+    return HUB_OK;
+}
+
+// Persistent launch of n FP32 CG iterations at L = 102 (k_cg_persist_sub), when the context
+// allows it and every workgroup of a device-filling grid is co-resident.  Returns HUB_OK with
+// *done = false when the two-kernel path must run instead (not applicable, or the cooperative
+// launch was refused: then never tried again on this context).
+hub_status try_persistent(hub_ctx* c, int nrhs, long long from, long long n, const PersistArgs<float>& base,
+                          hipStream_t st, bool* done) {
+    *done = false;
+    if (!c->persist_mode || !c->persist_ok || c->form != HUB_FORM_EXP || op_kind<float>(c, nrhs) != OpKind::Sub102)
+        return HUB_OK;
+    auto kern = k_cg_persist_sub<float, 102, kThreadsSub>;
+    const size_t lds = (size_t)(c->L * c->L + c->L) * sizeof(cx<float>);
+    allow_lds(kern, lds);
+    if (c->persist_grid < 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), kThreadsSub,
+                                                         lds) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+            (void)hipGetLastError();
+            per_cu = 0;
+        }
+        c->persist_grid = per_cu * cus;
+    }
+    if (c->persist_grid < 8) {
+        c->persist_ok = false;
+        return HUB_OK;
+    }
+    const int items = nrhs * c->Nt;
+    const int grid = std::min(items, c->persist_grid);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, c->persist_bar, 4);
+    hub_status s = launch_check("k_zero_u32");
+    if (s != HUB_OK) return s;
+    PersistArgs<float> a = base;
+    a.it0 = from;
+    a.n_iter = (int)n;
+    a.bar = c->persist_bar;
+    a.spin = c->persist_spin;
+    const OpTab<float> T = op_tab<float>(c);
+    void* args[] = {const_cast<OpTab<float>*>(&T), &a};
+    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(grid),
+                                                    dim3(kThreadsSub), args, (unsigned)lds, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->persist_ok = false;          // not co-resident after all: the two-kernel path from now on
+        return HUB_OK;
+    }
+    c->persist_launches += 1;
+    *done = true;
     return HUB_OK;
 }
 
@@ -475,6 +529,11 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
                        c->Nt, zero_start, FinInit{sc, o.tol, pr(0), pr(2), slots}, ra);
     hub_status s = launch_check("k_cg_init");
     if (s != HUB_OK) return s;
+    // the persistent launches' barrier state and abort flag start clear (the host reads the
+    // flag with the scalars at every check)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, c->persist_bar, 4);
+    s = launch_check("k_zero_u32");
+    if (s != HUB_OK) return s;
 
     auto reliable_update = [&](long long i) -> hub_status {
         hipLaunchKernelGGL(k_fold_solution<Rlo>, dim3(512, nrhs), dim3(kThreads), 0, st, xhi, xlo, c->N,
@@ -506,8 +565,19 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
         if (s != HUB_OK) return s;
     }
 
-    // Iterations i = from .. from + n - 1 (two kernels each).
+    // Iterations i = from .. from + n - 1: one persistent launch where it applies, else two
+    // kernels each.
+    c->persist_launches = 0;
     auto queue_iters = [&](long long from, long long n) -> hub_status {
+        if (n <= 0) return HUB_OK;
+        if constexpr (sizeof(Rlo) == sizeof(float)) {
+            if (!lin) {
+                const PersistArgs<float> pa{c->cg_pr, pt, sc, slots, nrhs, 0, 0, rlo, p, tv, xlo, tab_lo, nullptr, 0};
+                bool done = false;
+                const hub_status q = try_persistent(c, nrhs, from, n, pa, st, &done);
+                if (q != HUB_OK || done) return q;
+            }
+        }
         for (long long i = from; i < from + n; ++i) {
             const CtlSearch k1{pr(i), pr(i + 2), pt, sc, slots};
             const CtlUpdate k2{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
@@ -548,6 +618,8 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     std::vector<int> seen(nrhs, 0), stalled(nrhs, 0), logged(nrhs, 0);
     for (;;) {
         HIP_OR_FAIL(hipMemcpyAsync(c->scal_host, sc, nrhs * sizeof(CgScalars), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(hipMemcpyAsync(c->persist_flag_host, c->persist_bar, 4 * sizeof(unsigned), hipMemcpyDeviceToHost,
+                                   st));
         HIP_OR_FAIL(hipEventRecord(c->cg_event, st));
         const long long at = it;       // iterations behind the scalars being read
         const long long head = std::min<long long>(lookahead, o.max_iter - it);
@@ -555,6 +627,11 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
         if (s != HUB_OK) return s;
         it += head;
         HIP_OR_FAIL(hipEventSynchronize(c->cg_event));
+        if (c->persist_launches > 0 && c->persist_flag_host[2] != 0u) {
+            (void)hipStreamSynchronize(st);
+            return fail(HUB_ERR_DEVICE, "a grid barrier of the persistent CG launch gave up waiting "
+                                        "(spin limit %lld polls); x is undefined", c->persist_spin);
+        }
         bool all_done = true, bad = false, all_stalled = true;
         for (int r = 0; r < nrhs; ++r) {
             const CgScalars& h = c->scal_host[r];
@@ -606,6 +683,12 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     }
     // the iterations queued ahead end before the call returns
     HIP_OR_FAIL(hipStreamSynchronize(st));
+    if (c->persist_launches > 0) {
+        HIP_OR_FAIL(hipMemcpy(c->persist_flag_host, c->persist_bar, 4 * sizeof(unsigned), hipMemcpyDeviceToHost));
+        if (c->persist_flag_host[2] != 0u)
+            return fail(HUB_ERR_DEVICE, "a grid barrier of the persistent CG launch gave up waiting "
+                                        "(spin limit %lld polls); x is undefined", c->persist_spin);
+    }
     if (info) {
         for (int r = 0; r < nrhs; ++r) {
             const CgScalars& h = c->scal_host[r];
@@ -614,6 +697,7 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
             info[r].reliable_updates = h.reliable;
             info[r].true_rel_res = std::sqrt(h.true_rr / cc);
             info[r].recursive_rel_res = std::sqrt(h.rec_rr / cc);
+            info[r].persistent_launches = (int32_t)c->persist_launches;
         }
     }
     return result;
@@ -735,6 +819,8 @@ void hub_destroy(hub_ctx* c) {
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (c->scal_host) (void)hipHostFree(c->scal_host);
+    if (c->persist_flag_host) (void)hipHostFree(c->persist_flag_host);
+    if (c->persist_bar) (void)hipFree(c->persist_bar);
     if (c->tr_E_host) (void)hipHostFree(c->tr_E_host);
     if (c->cg_event) (void)hipEventDestroy(c->cg_event);
     delete c;
@@ -1041,6 +1127,15 @@ hub_status hub_trajectory(hub_ctx* c, double* phi, const double* pi0, const void
         info->dH = dH;
     }
     return finish(HUB_OK);
+}
+
+hub_status hub_set_cg_launch(hub_ctx* c, int32_t persistent, int64_t barrier_spin_limit) {
+    if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
+    if (persistent != 0 && persistent != 1) return fail(HUB_ERR_ARG, "persistent must be 0 or 1");
+    if (barrier_spin_limit < 0) return fail(HUB_ERR_ARG, "barrier_spin_limit must be >= 0");
+    c->persist_mode = persistent;
+    c->persist_spin = barrier_spin_limit > 0 ? (long long)barrier_spin_limit : (1LL << 24);
+    return HUB_OK;
 }
 
 hub_status hub_query(const hub_ctx* c, int32_t* path, int32_t* lds_bytes) {

@@ -77,6 +77,14 @@ struct hub_ctx {
     double* cg_pt = nullptr;             // ||M^dag p||^2 partials, [nrhs_max][max_partials]
     hub::CgScalars* scal_host = nullptr; // pinned host mirror
     hipEvent_t cg_event = nullptr;       // marks the copy of the scalars into scal_host
+    // persistent CG launches (FP32 iterations of the L = 102 sublattice kernel)
+    unsigned* persist_bar = nullptr;     // device [4]: arrivals, generation, abort flag
+    unsigned* persist_flag_host = nullptr;   // pinned mirror of the abort flag
+    int persist_mode = 0;                // 1: use when co-resident, 0: never (the default)
+    bool persist_ok = true;              // false once a cooperative launch was refused
+    long long persist_spin = 1LL << 24;  // polls before a barrier wait gives up
+    int persist_grid = -1;               // co-resident workgroups (-1: not yet known)
+    long long persist_launches = 0;      // during the current solve
     // HMC trajectory workspace (allocated on the first trajectory)
     void* tr_chi = nullptr;              // complex128 [nrhs_max][N]: the pseudofermions
     void* tr_x = nullptr;                // complex128 [nrhs_max][N]: the solutions

@@ -1070,8 +1070,8 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
 // written.  Two forward and two inverse sublattice transforms per slice, none repeated.
 // The loads of B's source are issued before A's column stages, so they arrive while those run.
 template <typename R, int L, int NT, class Src, class Epi, class Ctl>
-__global__ void __launch_bounds__(NT)
-k_fused_sub(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
+__device__ __forceinline__ void fused_sub_item(const OpTab<R>& T, const Src& src, const Epi& epi, const Ctl& ctl,
+                                               int u, cx<R>* buf, double* red_lds) {
     constexpr CPlan P = make_cplan(L);
     static_assert(P.nst >= 2, "needs a row stage besides the fused one");
     constexpr int LL = L * L;
@@ -1079,11 +1079,7 @@ k_fused_sub(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     constexpr int NTS = L * M0;                         // stage-0 tasks of one sublattice
     constexpr int ROUNDS = (NTS + NT - 1) / NT;
     constexpr int NP = (LL + NT - 1) / NT;              // momenta per thread in the mix
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red_lds[64];
-    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
     cx<R>* roots = buf + LL;
-    const int u = xcd_linear(blockIdx.x, gridDim.x);
     const int rhs = u / T.Nt, t = u - rhs * T.Nt;
     const int tid = threadIdx.x;
     static_assert(NT >= L, "one root of unity per thread");
@@ -1192,6 +1188,122 @@ k_fused_sub(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
         }
     }
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, t, sc, red_lds);
+}
+
+// The sublattice kernel proper: one workgroup per (right-hand side, slice).
+template <typename R, int L, int NT, class Src, class Epi, class Ctl>
+__global__ void __launch_bounds__(NT)
+k_fused_sub(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    fused_sub_item<R, L, NT>(T, src, epi, ctl, xcd_linear(blockIdx.x, gridDim.x), reinterpret_cast<cx<R>*>(smem),
+                             red_lds);
+}
+
+// ----------------------------------------------------------------------------- persistent CG
+// Grid-wide barrier of a cooperative launch (every workgroup co-resident).  bar[0] counts the
+// arrivals, bar[1] is the generation, bar[2] the abort flag.  Every wave waits for its own
+// stores, then thread 0 of each workgroup makes the workgroup's global writes visible
+// device-wide (agent-scope release), arrives, and the last
+// arrival opens the next generation; the others poll it.  Every wait is bounded: after `spin`
+// polls a waiting workgroup sets the abort flag, and a workgroup that sees the flag stops
+// waiting, so every workgroup leaves the barrier.  Returns false (in every thread) once the
+// flag is set: the caller returns, the host turns the flag into an error.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, long long spin) {
+    __shared__ int ok;
+    __builtin_amdgcn_s_waitcnt(0);       // this wave's stores have reached the L2 ...
+    __syncthreads();                     // ... in every wave, before thread 0's release
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned n = gridDim.x * gridDim.y * gridDim.z;
+        const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == n - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long polls = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+                if (++polls > spin) {
+                    __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        ok = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// Everything a persistent CG launch needs besides the operator tables.
+template <typename R>
+struct PersistArgs {
+    double* pr;                  // ||r||^2 partials, three rotating buffers of nrhs * slots
+    double* pt;                  // ||M^dag p||^2 partials
+    CgScalars* sc;
+    int slots, nrhs;
+    long long it0;               // first iteration of this launch (selects the rotating buffers)
+    int n_iter;
+    cx<R>* r;
+    cx<R>* p;
+    cx<R>* tv;
+    cx<R>* x;
+    PhTable<R> tab;
+    unsigned* bar;
+    long long spin;
+};
+
+// The two phases of a CG iteration on one item, kept out of line: inlined into the persistent
+// loop, the compiler would keep values of both phases live across it and spill.
+template <typename R, int L, int NT>
+__device__ __noinline__ void persist_search_item(const OpTab<R>& T, const PersistArgs<R>& a, const CtlSearch& k1,
+                                                 int u, cx<R>* buf, double* red_lds) {
+    fused_sub_item<R, L, NT>(T, SrcSearchNext<R>{a.r, a.p}, EpiSearchMdag<R, PhTable<R>>{a.r, a.p, a.tv, a.tab}, k1,
+                             u, buf, red_lds);
+}
+
+template <typename R, int L, int NT>
+__device__ __noinline__ void persist_update_item(const OpTab<R>& T, const PersistArgs<R>& a, const CtlUpdate& k2,
+                                                 int u, cx<R>* buf, double* red_lds) {
+    fused_sub_item<R, L, NT>(T, SrcPhasePrev<R, PhTable<R>>{a.tv, a.tab}, EpiUpdate<R>{a.tv, a.p, a.x, a.r}, k2, u,
+                             buf, red_lds);
+}
+
+// n_iter CG iterations (each: t = M^dag (r + beta p), then p, x, r updated with q = M t) in one
+// cooperative launch of the sublattice kernel's work: every workgroup loops over the
+// (right-hand side, slice) items of a phase, and a grid barrier separates the phases.  Item k
+// maps to the same slice and the same XCD as workgroup k of the two-kernel iteration, and does
+// the same arithmetic, so a persistent solve equals the two-kernel one bit for bit.
+template <typename R, int L, int NT>
+__global__ void __launch_bounds__(NT) k_cg_persist_sub(const OpTab<R> T, const PersistArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red_lds[64];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem);
+    const int items = a.nrhs * T.Nt;
+    const long long ns = (long long)a.nrhs * a.slots;
+    for (int n = 0; n < a.n_iter; ++n) {
+        const long long i = a.it0 + n;
+        double* pri = a.pr + (i % 3) * ns;
+        double* prm = a.pr + ((i + 2) % 3) * ns;
+        double* prn = a.pr + ((i + 1) % 3) * ns;
+        const CtlSearch k1{pri, prm, a.pt, a.sc, a.slots};
+        for (int k = blockIdx.x; k < items; k += gridDim.x)
+            persist_search_item<R, L, NT>(T, a, k1, xcd_linear(k, items), buf, red_lds);
+        if (!grid_barrier(a.bar, a.spin)) return;
+        const CtlUpdate k2{pri, prm, a.pt, prn, a.sc, a.slots};
+        for (int k = blockIdx.x; k < items; k += gridDim.x)
+            persist_update_item<R, L, NT>(T, a, k2, xcd_linear(k, items), buf, red_lds);
+        if (n + 1 < a.n_iter && !grid_barrier(a.bar, a.spin)) return;
+    }
+}
+
+// zero n words (the barrier state before a persistent launch; a kernel, not a memset node)
+__global__ void k_zero_u32(unsigned* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
 // e^{i phi} as a table, evaluated in FP64 and rounded once to R

@@ -13,9 +13,9 @@ int main(void) {
            offsetof(hub_cg_opts, max_iter), offsetof(hub_cg_opts, reliable_every), offsetof(hub_cg_opts, prec),
            offsetof(hub_cg_opts, use_x0), offsetof(hub_cg_opts, stall_updates), offsetof(hub_cg_opts, history_host),
            offsetof(hub_cg_opts, history_len));
-    printf("hub_cg_info %zu %zu %zu %zu %zu\n", sizeof(hub_cg_info), offsetof(hub_cg_info, iters),
+    printf("hub_cg_info %zu %zu %zu %zu %zu %zu\n", sizeof(hub_cg_info), offsetof(hub_cg_info, iters),
            offsetof(hub_cg_info, reliable_updates), offsetof(hub_cg_info, true_rel_res),
-           offsetof(hub_cg_info, recursive_rel_res));
+           offsetof(hub_cg_info, recursive_rel_res), offsetof(hub_cg_info, persistent_launches));
     printf("hub_traj_opts %zu %zu %zu %zu %zu %zu\n", sizeof(hub_traj_opts), offsetof(hub_traj_opts, U),
            offsetof(hub_traj_opts, eps), offsetof(hub_traj_opts, n_md), offsetof(hub_traj_opts, integrator),
            offsetof(hub_traj_opts, cg));

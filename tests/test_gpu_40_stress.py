@@ -43,13 +43,55 @@ def test_stress_cg_heat_bath(stress, prec):
         assert np.linalg.norm(y - rho[k]) <= 1e-6 * np.linalg.norm(rho[k])
 
 
-def test_stress_batched_equals_single(stress):
-    """The 4-rhs launch does per-rhs arithmetic identical to a 1-rhs solve."""
+@pytest.mark.parametrize("persistent", [False, True])
+def test_stress_batched_equals_single(stress, persistent):
+    """The 4-rhs launch does per-rhs arithmetic identical to a 1-rhs solve, with two launches per
+    iteration and with the persistent launch (every right-hand side's FP32 iterations in one
+    cooperative launch per block of iterations)."""
     w, hub, op, phi, rho, P, chi = stress
-    res4 = hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=20000)
-    res1 = hub.cg_solve(P, chi[2:3].contiguous(), tol=1e-10, prec="mixed", max_iter=20000)
+    try:
+        hub.set_cg_launch(persistent=persistent)
+        res4 = hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=20000)
+        res1 = hub.cg_solve(P, chi[2:3].contiguous(), tol=1e-10, prec="mixed", max_iter=20000)
+    finally:
+        hub.set_cg_launch(persistent=False)
+    assert (res4.persistent_launches > 0) == persistent and (res1.persistent_launches > 0) == persistent
     assert res4.iters[2] == res1.iters[0]
     assert torch.equal(res4.x[2], res1.x[0])
+
+
+def test_stress_persistent_equals_two_kernel_iterations(stress):
+    """The persistent launch (grid barriers between the M^dag and M phases) and two launches per
+    iteration give the same solution bit for bit, with the same iteration counts."""
+    w, hub, op, phi, rho, P, chi = stress
+    print("[case] stress persistent vs two-kernel", flush=True)
+    two = hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=20000)
+    try:
+        hub.set_cg_launch(persistent=True)
+        per = hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=20000)
+    finally:
+        hub.set_cg_launch(persistent=False)
+    assert two.persistent_launches == 0 and per.persistent_launches > 0
+    assert two.iters == per.iters
+    assert torch.equal(two.x, per.x)
+
+
+def test_stress_persistent_barrier_wait_gives_up(stress):
+    """A grid-barrier wait bounded to a single poll (forced from the host) runs out: every
+    workgroup leaves the launch and the solve returns HUB_ERR_DEVICE; the next solve, with the
+    default bound, is unaffected."""
+    from paper_2210_06874_amd import HubError
+    w, hub, op, phi, rho, P, chi = stress
+    print("[case] stress persistent barrier give-up", flush=True)
+    try:
+        hub.set_cg_launch(persistent=True, barrier_spin_limit=1)
+        with pytest.raises(HubError, match="HUB_ERR_DEVICE"):
+            hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=100)
+        hub.set_cg_launch(persistent=True, barrier_spin_limit=0)
+        res = hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=20000)
+    finally:
+        hub.set_cg_launch(persistent=False)
+    assert res.converged and res.persistent_launches > 0
 
 
 def test_stress_force(stress):
