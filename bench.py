@@ -7,14 +7,15 @@ dS/dphi.  `value` is the sustained rate of operator applications (M or M^dag, ea
 counted once; per CG iteration 2, per FP64 residual recomputation 2, the force 1)
 over the timed steps.
 
-The input field is labelled: phi drawn from N(0, sqrt(delta U)) and scaled by
-delta ("weak field"), chi iid Gaussian.  With the unscaled prior draws (not
-thermalised by the weight det(M M^dag)) M M^dag is so ill-conditioned at beta = 8
-that the CG does not converge; their per-iteration cost is reported separately
-(--literal-probe).
+The input is the field an HMC force sees (Sec. 2): the stored HMC field of this lattice
+(workloads/field_L51_Nt128_U3.85_hmc.npz, made by the library's own trajectories from a
+cold start; its M M^dag carries the weight det(M M^dag)), with the heat-bath pseudofermion
+chi = M rho.  The Gaussian prior draws alone are not solvable at beta = 8 (the CG stalls;
+their per-iteration cost is reported by --literal-probe).
 
 Also measured (not part of `value`):
   * the FP64 force step (s per force, FP64 vs mixed);
+  * the same force step on the labelled "weak field" (prior draws scaled by delta, iid chi);
   * back-to-back hub_apply_M_c64 / hub_apply_M launches timed with HIP events on
     the launching stream: the roofline of the dominant kernel;
   * the same force step with the linear form of the operator (eq. "ferm_op" as printed,
@@ -22,9 +23,10 @@ Also measured (not part of `value`):
   * the CPU oracle (rank 0, N = 1 only) on a bounded sample of operator applications.
 
 `--stress` replaces all of this by the four-right-hand-side L = 102, Nt = 192 workload
-(operator launches for all four vectors, mixed CG iterations).
+(operator launches for all four vectors, mixed CG iterations); `--copy-floor` by plain
+device copies of the same byte counts.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--stress]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--stress] [--copy-floor]
 """
 from __future__ import annotations
 
@@ -191,12 +193,16 @@ def nrhs_scan(w, dev) -> dict:
     return out
 
 
-def linear_leg(w, dev, P, C, P32, V32, out32, steps: int, warmup: int) -> dict:
-    """The force step and the FP32 apply roofline with the linear form of the operator."""
+def linear_leg(w, dev, P32, V32, out32, steps: int, warmup: int) -> dict:
+    """The force step (on the weak field: the HMC field belongs to the exponential form's
+    weight) and the FP32 apply roofline with the linear form of the operator."""
     import torch
     from paper_2210_06874_amd import Hubbard
+    from workloads import draw_weak_field
+    phi_w, chi_w = draw_weak_field(w)
+    P, C = torch.from_numpy(phi_w).to(dev), torch.from_numpy(chi_w).to(dev)
     hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, device=dev, form="linear")
-    out = {}
+    out = {"input": "weak field (phi = delta * prior draws), chi iid"}
     for prec in ("mixed", "fp64"):
         for _ in range(max(1, warmup)):
             hub.cg_solve(P, C, tol=1e-10, prec=prec, max_iter=200000)
@@ -272,6 +278,51 @@ def stress_leg(dev, steps: int) -> dict:
                       "launches per iteration"}
 
 
+def weak_field_leg(w, dev, hub, steps: int) -> dict:
+    """The force step on the labelled weak field (prior draws scaled by delta, iid chi): a
+    nearly free operator, the stand-in input before an HMC field existed."""
+    import torch
+    from workloads import draw_weak_field
+    phi_w, chi_w = draw_weak_field(w)
+    P, C = torch.from_numpy(phi_w).to(dev), torch.from_numpy(chi_w).to(dev)
+    out = {"input": "phi = delta * N(0, sqrt(delta U)) prior draws, chi iid"}
+    for prec in ("mixed", "fp64"):
+        res = hub.cg_solve(P, C, tol=1e-10, prec=prec, max_iter=200000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = hub.cg_solve(P, C, tol=1e-10, prec=prec, max_iter=200000)
+            hub.force(P, res.x)
+            hub.action(C, res.x)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        out[prec] = {"s_per_force": el, "cg_iters": res.iters[0], "reliable_updates": res.reliable_updates[0],
+                     "true_rel_res": res.true_rel_res[0],
+                     "applications_per_s": (2 * res.iters[0] + 2 * res.reliable_updates[0] + 1) / el}
+    return out
+
+
+def copy_floor(w, dev) -> dict:
+    """The time a plain device-to-device copy (torch's copy kernel, captured in a HIP graph)
+    takes to move as many bytes (read + write) as one operator application at L = 51,
+    Nt = 128, and at larger sizes: what launch ramp and memory latency leave of the 8 TB/s
+    at each size."""
+    import torch
+    out = {"what": "device-to-device copy, HIP graph of 50 launches, events on its stream",
+           "sizes": []}
+    cases = [("FP32 application bytes", 20.0 * w.N), ("FP64 application bytes", 40.0 * w.N),
+             ("64 MiB", 64.0 * 2 ** 20), ("256 MiB", 256.0 * 2 ** 20), ("1 GiB", 2.0 ** 30)]
+    for name, moved in cases:
+        n = int(moved // 2) // 4                       # float32 elements read (and written)
+        a = torch.full((n,), 1.0, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        t = time_graph(lambda: b.copy_(a), per_graph=50, replays=10)
+        out["sizes"].append({"case": name, "bytes_moved": 8.0 * n, "us": t * 1e6,
+                             "GBs": 8.0 * n / t / 1e9, "frac_of_hbm_peak": 8.0 * n / t / 1e9 / HBM_PEAK_GBS})
+        del a, b
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +333,9 @@ def main() -> int:
                     help="CG iterations to time on the unscaled prior field (0: skip)")
     ap.add_argument("--probe", action="store_true",
                     help="only run 20 FP32 operator launches and a 64 MiB copy (for counter runs)")
+    ap.add_argument("--copy-floor", action="store_true",
+                    help="only time plain device-to-device copies (HIP graphs) moving the bytes of one "
+                         "FP32 / FP64 operator application and larger sizes, one JSON line")
     ap.add_argument("--stress", action="store_true",
                     help="instead of the force step: the four-right-hand-side L = 102, Nt = 192 "
                          "workload (operator launches and mixed CG iterations), one JSON line")
@@ -296,7 +350,7 @@ def main() -> int:
     import torch
 
     from paper_2210_06874_amd import Hubbard
-    from workloads import PREC, draw_inputs, draw_weak_field
+    from workloads import PREC, draw_complex, draw_inputs, load_hmc_field
 
     w = PREC
     dev = torch.device("cuda", 0)
@@ -321,12 +375,17 @@ def main() -> int:
     if args.stress:
         print(json.dumps(stress_leg(dev, args.steps)))
         return 0
-    phi_w, chi_w = draw_weak_field(w)
+    if args.copy_floor:
+        print(json.dumps(copy_floor(w, dev)))
+        return 0
+    # the headline input: the stored HMC field, heat-bath chi = M rho (rho seeded)
+    phi_h, field_meta = load_hmc_field()
+    rho_h = draw_complex(w, seed=11)
     hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, device=dev)
-    P = torch.from_numpy(phi_w).to(dev)
-    C = torch.from_numpy(chi_w).to(dev)
+    P = torch.from_numpy(phi_h).to(dev)
+    C = hub.apply_M(P, torch.from_numpy(rho_h).to(dev))
 
-    def step(prec):
+    def step(prec, P=P, C=C):
         res = hub.cg_solve(P, C, tol=1e-10, prec=prec, max_iter=200000)
         g = hub.force(P, res.x)
         S = hub.action(C, res.x)
@@ -358,6 +417,7 @@ def main() -> int:
     g_mixed = g.cpu().numpy()
     g_fp64 = g64.cpu().numpy()
     force_diff = float(np.linalg.norm(g_mixed - g_fp64) / np.linalg.norm(g_fp64))
+    weak = weak_field_leg(w, dev, hub, max(1, args.steps // 2))
 
     # dominant kernel: the FP32 operator the mixed CG iterates with (same template and launch)
     P32 = P.float()
@@ -386,7 +446,7 @@ def main() -> int:
     roof64 = {"achieved": alg64 / t_k64 / 1e9, "frac": alg64 / t_k64 / 1e9 / HBM_PEAK_GBS,
               "avg_launch_us": t_k64 * 1e6, "alg_bytes_per_launch": alg64}
 
-    lin = linear_leg(w, dev, P, C, P32, V32, out32, args.steps, args.warmup)
+    lin = linear_leg(w, dev, P32, V32, out32, args.steps, args.warmup)
     batching = nrhs_scan(w, dev)
 
     # the timed step is almost all CG iterations: two operator kernels that move 96 B per
@@ -434,7 +494,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "L51_Nt128 weak-field (phi = delta * N(0, sqrt(delta U)), chi iid), "
+        "config": {"workload": f"L51_Nt128 HMC field ({field_meta['trajectories']} trajectories from phi = 0 at "
+                               f"U = {field_meta['U']}, rms {field_meta['phi_rms']:.3f}), heat-bath chi = M rho; "
                                "one HMC force: mixed CG to 1e-10 + action + force",
                    "L": w.L, "Nt": w.Nt, "beta": w.beta, "U": w.U, "kappa": w.kappa, "nrhs": 1,
                    "parallelism": "single GPU"},
@@ -446,6 +507,7 @@ def main() -> int:
         "cg_true_rel_res_mixed": last.true_rel_res[0],
         "cg_iters_fp64": res64.iters[0],
         "force_rel_diff_mixed_vs_fp64": force_diff,
+        "weak_field": weak,
         "roofline": roof,
         "roofline_apply_M_fp64": roof64,
         "linear_form": lin,
@@ -454,7 +516,9 @@ def main() -> int:
         "cpu_baseline": None,
     }
     if not args.no_cpu and int(os.environ.get("RANK", "0")) == 0:
-        line["cpu_baseline"] = cpu_baseline(w, phi_w, chi_w, res64.iters[0])
+        # the oracle's cost per application and per iteration does not depend on the values: it
+        # is timed on the same field with rho (a seeded draw) as the vector
+        line["cpu_baseline"] = cpu_baseline(w, phi_h, rho_h, res64.iters[0])
     print(json.dumps(line))
     return 0
 
