@@ -45,6 +45,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "M-applications/s & s per HMC force, L=51 Nt=128, FP32-mixed vs FP64 @1e-10 res"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_M_c64_L51_Nt128.txt")
 TRAFFIC_FILE_LIN = os.path.join(ROOT, "profiles", "traffic_apply_M_c64_linear_L51_Nt128.txt")
+TRAFFIC_FILE_TR = os.path.join(ROOT, "profiles", "traffic_apply_M_c64_transform_L51_Nt128.txt")
 KERNEL_SOURCES = ["hub_fft.hpp", "hub_kernels.hpp", "hub_math.hpp", "hub_abi.hip", "hub_tables.cpp",
                   "hub_tables.hpp", "hub_internal.hpp"]
 
@@ -361,10 +362,10 @@ def main() -> int:
         V32 = torch.from_numpy(chi).to(dev).to(torch.complex64)
         out32 = torch.empty_like(V32)
         hub_lin = Hubbard(w.L, w.Nt, w.beta, w.kappa, device=dev, form="linear")
-        for _ in range(20):
-            hub.apply_M_c64(P32, V32, out=out32)
-        for _ in range(20):
-            hub_lin.apply_M_c64(P32, V32, out=out32)
+        hub_tr = Hubbard(w.L, w.Nt, w.beta, w.kappa, device=dev, path="fused")
+        for h in (hub, hub_lin, hub_tr):        # Taylor stencil, linear stencil, transforms
+            for _ in range(20):
+                h.apply_M_c64(P32, V32, out=out32)
         a = torch.full((16 * 1024 * 1024,), 1.0, dtype=torch.float32, device=dev)   # 64 MiB
         b = torch.empty_like(a)
         for _ in range(5):
@@ -430,19 +431,32 @@ def main() -> int:
     alg32 = 20.0 * w.N          # read v (8N) + phi (4N), write out (8N)
     alg64 = 40.0 * w.N
     traffic = read_traffic(TRAFFIC_FILE)
-    # the FFT convention 5 n log2 n flops per complex transform of n points: four L x L
-    # transforms per slice (two sublattices, forward and inverse)
-    fft_flops = w.Nt * 4 * 5.0 * w.L ** 2 * math.log2(w.L ** 2)
+    # the degree-6 Taylor stencil: per site and sweep, K (two complex adds, 4 flops) and the
+    # Horner update (one complex scale-add, 4 flops); the phase product (6) and the epilogue (2)
+    tay_flops = w.N * (6 * 8.0 + 6.0 + 2.0)
     roof = {"bound": "hbm", "achieved": alg32 / t_k32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": alg32 / t_k32 / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "hub_apply_M_c64 (k_fused_ct<float, 51, ...> two workgroups per slice)",
+            "kernel": "hub_apply_M_c64 (k_taylor<float, 51, 512, 6>: degree-6 Taylor stencil, two "
+                      "workgroups per slice)",
             "avg_launch_us": t_k32 * 1e6, "avg_launch_us_python_loop": t_loop32 * 1e6,
             "alg_bytes_per_launch": alg32, "site_slices_per_s": w.N / t_k32,
-            "alu": {"flops_per_launch": fft_flops, "achieved_tflops": fft_flops / t_k32 / 1e12,
+            "alu": {"flops_per_launch": tay_flops, "achieved_tflops": tay_flops / t_k32 / 1e12,
                     "peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
-                    "frac": fft_flops / t_k32 / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
-                    "convention": "5 n log2 n per complex transform, 4 transforms of L^2 points per slice"},
+                    "frac": tay_flops / t_k32 / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                    "convention": "6 sweeps x 8 flops + phase 6 + epilogue 2 per site-slice"},
             "timing": "HIP graph of 50 launches, events on its stream"}
+    # the same application by the transform kernels (the forced fused path; every FP64 operator
+    # and larger delta kappa use them)
+    hub_tr = Hubbard(w.L, w.Nt, w.beta, w.kappa, device=dev, path="fused")
+    t_tr = time_graph(lambda: hub_tr.apply_M_c64(P32, V32, out=out32))
+    fft_flops = w.Nt * 4 * 5.0 * w.L ** 2 * math.log2(w.L ** 2)
+    roof_tr = {"kernel": "k_fused_ct<float, 51, 512, true>: two 2-D transforms forward, the 2 x 2 mix, "
+                         "one back per workgroup, two workgroups per slice",
+               "avg_launch_us": t_tr * 1e6, "achieved": alg32 / t_tr / 1e9,
+               "frac": alg32 / t_tr / 1e9 / HBM_PEAK_GBS,
+               "traffic": read_traffic(TRAFFIC_FILE_TR),
+               "alu_tflops_5nlog2n": fft_flops / t_tr / 1e12}
+    del hub_tr
     roof64 = {"achieved": alg64 / t_k64 / 1e9, "frac": alg64 / t_k64 / 1e9 / HBM_PEAK_GBS,
               "avg_launch_us": t_k64 * 1e6, "alg_bytes_per_launch": alg64}
 
@@ -510,6 +524,7 @@ def main() -> int:
         "weak_field": weak,
         "roofline": roof,
         "roofline_apply_M_fp64": roof64,
+        "roofline_apply_M_fp32_transform": roof_tr,
         "linear_form": lin,
         "batching": batching,
         "literal_field_probe": probe,

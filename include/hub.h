@@ -78,8 +78,10 @@ typedef enum {
 typedef enum { HUB_PREC_FP64 = 0, HUB_PREC_MIXED = 1 } hub_prec;
 
 /* Which kernel layout applies E: AUTO picks the fused one-slice-per-workgroup
- * kernel when a slice fits in LDS, else the three-kernel split path.  FUSED and
- * SPLIT force one (FUSED fails with HUB_ERR_ARG when the slice does not fit). */
+ * kernel when a slice fits in LDS, else the three-kernel split path, and at L = 51 with
+ * 3 |delta kappa| <= 0.25 the Taylor-polynomial stencil for the FP32 operators (see
+ * hub_apply_M_c64).  FUSED and SPLIT force one (FUSED fails with HUB_ERR_ARG when the slice
+ * does not fit); both apply E through the transforms in both precisions. */
 typedef enum { HUB_PATH_AUTO = 0, HUB_PATH_FUSED = 1, HUB_PATH_SPLIT = 2 } hub_path;
 
 /* Which fermion matrix the context applies (see the top of this file). */
@@ -144,7 +146,11 @@ hub_status hub_apply_Mdag(hub_ctx* ctx, const double* phi, const void* in, void*
                           int32_t nrhs, void* stream);
 
 /* FP32 variants of the two operators (complex64 vectors, float phi): the kernels
- * that the mixed-precision CG iterates with. */
+ * that the mixed-precision CG iterates with.  With HUB_PATH_AUTO at L = 51 and
+ * 3 |delta kappa| <= 0.25 they apply E = e^{delta mu} exp(delta kappa K) (Sec. 2, eq.
+ * "ferm_op") as its degree-6 Taylor polynomial in delta kappa K, whose truncation is at most
+ * 1.3e-8 relative (K's spectrum lies in [-3, 3]), below FP32 rounding; otherwise, and in
+ * every FP64 entry point, through the per-slice transforms. */
 hub_status hub_apply_M_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,
                            int32_t nrhs, void* stream);
 hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,

@@ -18,6 +18,12 @@ constexpr int kThreads51 = 512;     // workgroup size of the L = 51 kernels
 // the minimum-norm choice of the Omelyan-Mryglod-Folk second-order integrator
 constexpr double kOmelyanLambda = 0.1931833275037836;
 constexpr int kHalfBelow = 256;     // two workgroups per slice below this many slices
+// FP32 operators at L = 51 by the degree-6 Taylor polynomial of exp(delta kappa K) while
+// x = 3 |delta kappa| <= 0.25: its remainder, at most x^7/7! e^x, is then under 1.3e-8, a fifth
+// of FP32's unit roundoff (larger steps, and every FP64 operator, take the FFT kernels)
+constexpr double kTaylorMaxX = 0.25;
+constexpr int kTaylorDeg = 6;
+constexpr int kThreadsTaylor = 512;   // 16 strips (half waves) of 3-4 rows; 768 and 1024 measured slower in CG
 
 thread_local char g_err[512] = "";
 
@@ -122,7 +128,7 @@ void allow_lds(K kern, size_t bytes) {
 
 // Which operator kernel runs for nrhs right-hand sides, and how many reduction slots
 // (blocks per right-hand side) it has.
-enum class OpKind { Generic, Whole51, Half51, Split, Linear, Sub102 };
+enum class OpKind { Generic, Whole51, Half51, Taylor51, Split, Linear, Sub102 };
 
 // Workgroup size of the sublattice-at-a-time kernel.  Its 84 KB tile allows one workgroup
 // per compute unit, so the waves per CU are the workgroup's own: twelve (three per SIMD)
@@ -154,6 +160,7 @@ OpKind op_kind(const hub_ctx* c, int nrhs) {
         if (!c->split_forced && c->specialized && c->L == 102 && sizeof(R) == sizeof(float)) return OpKind::Sub102;
         return OpKind::Split;
     }
+    if (c->L == 51 && c->specialized && c->taylor && sizeof(R) == sizeof(float)) return OpKind::Taylor51;
     if (c->L == 51 && c->specialized) return nrhs * c->Nt < kHalfBelow ? OpKind::Half51 : OpKind::Whole51;
     return OpKind::Generic;
 }
@@ -161,7 +168,8 @@ OpKind op_kind(const hub_ctx* c, int nrhs) {
 template <typename R>
 int op_slots(const hub_ctx* c, int nrhs) {
     switch (op_kind<R>(c, nrhs)) {
-        case OpKind::Half51: return 2 * c->Nt;
+        case OpKind::Half51:
+        case OpKind::Taylor51: return 2 * c->Nt;
         case OpKind::Split: return 2 * c->Nt * split_geom(c->L).nrb;
         case OpKind::Linear: return c->Nt * lin_nch(c, nrhs);
         default: return c->Nt;
@@ -216,6 +224,15 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
             allow_lds(kern, lds);
             hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
             return launch_check("k_fused_ct<51, half>");
+        }
+        case OpKind::Taylor51: {
+            if constexpr (sizeof(R) == sizeof(float)) {
+                auto kern = k_taylor<R, 51, kThreadsTaylor, kTaylorDeg, Src, Epi, Ctl>;
+                hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreadsTaylor), 0, st, T,
+                                   (R)(c->delta * c->kappa), (R)std::exp(c->delta * c->mu), src, epi, ctl);
+                return launch_check("k_taylor<51>");
+            }
+            return fail(HUB_ERR_ARG, "internal: the Taylor kernel is FP32 only");
         }
         case OpKind::Whole51: {
             auto kern = k_fused_ct<R, 51, kThreads51, false, Src, Epi, Ctl>;
@@ -765,6 +782,8 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     c->path = (prm->path == HUB_PATH_SPLIT || (prm->path == HUB_PATH_AUTO && !fits)) ? HUB_PATH_SPLIT
                                                                                       : HUB_PATH_FUSED;
     c->split_forced = prm->path == HUB_PATH_SPLIT;
+    c->taylor = !lin && prm->path == HUB_PATH_AUTO && c->path == HUB_PATH_FUSED && c->L == 51 &&
+                3.0 * std::fabs(c->delta * c->kappa) <= kTaylorMaxX;
 
     std::vector<double> roots, etab;
     if (!lin) build_tables(plan, c->delta * c->kappa, c->delta * prm->mu, roots, etab);

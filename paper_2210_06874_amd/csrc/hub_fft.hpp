@@ -381,6 +381,45 @@ __device__ __forceinline__ void ct_stage(cx<R>* __restrict__ buf, const cx<R>* _
     constexpr int RAD = P.radix[Q], LQ = P.len[Q], M = LQ / RAD, PER = L / RAD;
     constexpr int NL = NS * L, NTASK = NL * PER, TWS = L / LQ;
     constexpr int ST = COLS ? M * L : M;
+    // a twiddle-free odd stage whose butterflies fill more than half of the lanes but fewer
+    // than all: the first half of the workgroup takes whole butterflies, the rest are shared
+    // by lane pairs on the second half (FP32), so no SIMD runs two full-butterfly waves
+    if constexpr (kPairOddStages && sizeof(R) == sizeof(float) && RAD >= 5 && M == 1 && 2 * NTASK > NT &&
+                  NTASK < NT && 2 * (NTASK - NT / 2) <= NT / 2) {
+        constexpr int NH = NT / 2, NR = NTASK - NH;
+        auto base_of = [](int task) {
+            if constexpr (COLS) {
+                const int b = task / NL, line = task - b * NL;
+                const int s = line >= L ? 1 : 0;
+                return s * L * L + (line - s * L) + b * LQ * L;
+            } else {
+                const int line = task / PER, b = task - line * PER;
+                return line * L + b * LQ;
+            }
+        };
+        const int tid = threadIdx.x;
+        if (tid < NH) {
+            const int base = base_of(tid);
+            cx<R> x[RAD];
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) x[i] = buf[base + i * ST];
+            small_dft_ct<R, RAD, INV>(x);
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) buf[base + i * ST] = x[i];
+        } else if (tid < NH + 2 * NR) {
+            const int t2 = tid - NH, q = t2 & 1;
+            const int base = base_of(NH + (t2 >> 1));
+            cx<R> x[RAD];
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) x[i] = buf[base + i * ST];
+            R y[RAD];
+            small_dft_pair<R, RAD, INV>(x, q, y);
+            R* comp = reinterpret_cast<R*>(buf) + q;
+#pragma unroll
+            for (int i = 0; i < RAD; ++i) comp[2 * (base + i * ST)] = y[i];
+        }
+        return;
+    }
     if constexpr (kPairOddStages && sizeof(R) == sizeof(float) && RAD >= 5 && M == 1 && 2 * NTASK <= NT) {
         for (int t2 = threadIdx.x; t2 < 2 * NTASK; t2 += NT) {
             const int task = t2 >> 1, q = t2 & 1;

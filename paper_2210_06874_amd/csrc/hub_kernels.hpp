@@ -1061,6 +1061,158 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
 }
 
+// ----------------------------------------------------------------------------- Taylor kernel
+// E = e^{delta mu} exp(delta kappa K) applied as its Taylor polynomial of degree DEG, evaluated by
+// Horner's rule y <- v + (delta kappa / j) K y, j = DEG..1: DEG nearest-neighbour stencil
+// sweeps over the slice instead of four L x L transforms.  The remainder after degree DEG is
+// at most x^{DEG+1}/(DEG+1)! e^x with x = 3 |delta kappa| (the largest eigenvalue of K is 3);
+// the host uses this kernel only where that is far below the precision's rounding.
+//
+// Two workgroups per slice split the columns n2: workgroup h writes columns [h*(L/2), ...) and
+// carries H = ceil(DEG/2) halo columns on each side, since each pair of sweeps widens a
+// site's dependence by one column each way (A(n) reaches B(n - e2), B(m) reaches A(m + e2)).
+// Lanes run along n2 (32 lanes per strip when the columns and halos fit, so a strip is half a
+// wave, else 64; a site's n2 neighbours are the adjacent lanes, fetched with wave-wide DPP
+// shifts, and the lanes at a strip's two edges receive another strip's values or 0, which only
+// ever feed halo columns).  FP32 only: in FP64 (degree 12, two 32-bit shifts per value, 64-lane
+// strips) the FFT kernels measured faster.  Rows n1 (periodic, all
+// L of them) are split into NT/32 strips of at most RMAX rows held in registers; the row above
+// and below a strip cross strips through LDS once per sweep.
+template <int L, int NT, int DEG>
+struct TayGeom {
+    static constexpr int H = (DEG + 1) / 2;
+    static constexpr int W = L - L / 2 + 2 * H;          // widest column range with its halos
+    static constexpr int LPS = W <= 32 ? 32 : 64;        // lanes (columns) per strip
+    static constexpr int NSTRIP = NT / LPS;
+    static constexpr int RMAX = (L + NSTRIP - 1) / NSTRIP;
+    static_assert(W <= LPS, "column range and halos must fit one strip");
+    static_assert(NT % 64 == 0, "whole waves");
+};
+
+// Wave-wide lane shifts (DPP): lane i receives lane i - 1 (prev) or i + 1 (next); the lane
+// that has no such neighbour receives 0.  The compiler folds them into the adds that use them.
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ cx<float> lane_prev(cx<float> v) {
+    return {lane_shift<kDppWaveShr1>(v.re), lane_shift<kDppWaveShr1>(v.im)};
+}
+__device__ __forceinline__ cx<float> lane_next(cx<float> v) {
+    return {lane_shift<kDppWaveShl1>(v.re), lane_shift<kDppWaveShl1>(v.im)};
+}
+
+template <typename R, int L, int NT, int DEG, class Src, class Epi, class Ctl>
+__global__ void __launch_bounds__(NT)
+k_taylor(const OpTab<R> T, const R dk, const R emu, const Src src, const Epi epi, const Ctl ctl) {
+    static_assert(sizeof(R) == sizeof(float), "FP32 only: in FP64 the FFT kernels measured faster");
+    using G = TayGeom<L, NT, DEG>;
+    constexpr int LL = L * L, RM = G::RMAX, NS = G::NSTRIP;
+    __shared__ cx<R> edgeA[2][NS][G::LPS];               // first row's A of each strip, per sweep parity
+    __shared__ cx<R> edgeB[2][NS][G::LPS];               // last row's B
+    __shared__ double red_lds[64];
+    const int u = xcd_linear(blockIdx.x, gridDim.x);
+    const int q = u >> 1, h = u & 1;
+    const int rhs = q / T.Nt, t = q - rhs * T.Nt;
+    const int slot = 2 * t + h;
+    const int tid = threadIdx.x;
+    const int s = tid / G::LPS, j = tid - s * G::LPS;
+    const int r0 = s * L / NS, nr = (s + 1) * L / NS - r0;
+    const int c0 = h * (L / 2), ncol = h ? L - L / 2 : L / 2;
+    const int n2 = (c0 - G::H + j + L) % L;
+    const bool out_lane = j >= G::H && j < G::H + ncol;
+    // every global load before the block's CG scalars (as in k_fused_ct): partials, source
+    // entries, then the epilogue operands of this lane's output sites
+    typename Ctl::Pre cpre = ctl.prefetch(rhs);
+    const int ts = src.slice(t, T.Nt);
+    typename Src::Pre pa[RM], pb[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const int n1 = r0 + min(r, nr - 1);                // rows past the strip repeat its last row
+        pa[r] = src.fetch(rhs, ts, n1 * L + n2, T);
+        pb[r] = src.fetch(rhs, ts, LL + n1 * L + n2, T);
+    }
+    // epilogue operands with the source when they fit a register budget of 64 (held across
+    // the sweeps), else fetched after the sweeps
+    constexpr bool kEpiEarly = sizeof(typename Epi::Pre) * 2 * RM <= 256;
+    typename Epi::Pre ea[RM], eb[RM];
+    auto fetch_epi = [&]() {
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+            const int n1 = r0 + min(r, nr - 1);
+            ea[r] = epi.fetch(rhs, t, n1 * L + n2, T);
+            eb[r] = epi.fetch(rhs, t, LL + n1 * L + n2, T);
+        }
+    };
+    if constexpr (kEpiEarly) fetch_epi();
+    const Scal sc = ctl.begin(rhs, slot, red_lds, cpre);
+    auto early_epi = [&]() {
+        if (out_lane) {
+#pragma unroll
+            for (int r = 0; r < RM; ++r)
+                if (r < nr) {
+                    epi_early<R>(epi, rhs, t, (r0 + r) * L + n2, ea[r], T, sc);
+                    epi_early<R>(epi, rhs, t, LL + (r0 + r) * L + n2, eb[r], T, sc);
+                }
+        }
+    };
+    double acc = 0.0;
+    if (sc.open) {
+        cx<R> va[RM], vb[RM], ya[RM], yb[RM];
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+            va[r] = src.make(pa[r], sc);
+            vb[r] = src.make(pb[r], sc);
+            ya[r] = va[r];
+            yb[r] = vb[r];
+        }
+        if constexpr (kEpiEarly) early_epi();
+        const int sp = (s + NS - 1) % NS, sn = (s + 1) % NS;
+#pragma unroll
+        for (int k = DEG; k >= 1; --k) {
+            const int par = k & 1;
+            cx<R> lastb = yb[0];
+#pragma unroll
+            for (int r = 1; r < RM; ++r)
+                if (r < nr) lastb = yb[r];
+            edgeA[par][s][j] = ya[0];
+            edgeB[par][s][j] = lastb;
+            __syncthreads();
+            const cx<R> above = edgeB[par][sp][j];        // B of row r0 - 1 (the previous strip's last)
+            const cx<R> below = edgeA[par][sn][j];        // A of row r0 + nr (the next strip's first)
+            const R ck = dk * (R)(1.0 / k);
+            // rows top to bottom, in place: row r's new A needs the old B of rows r and r - 1
+            // (the latter carried in bup), its new B the old A of rows r and r + 1 (not yet
+            // updated when row r is)
+            cx<R> bup = above;
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                const cx<R> adn = (r + 1 < RM && r + 1 < nr) ? ya[r + 1 < RM ? r + 1 : 0] : below;
+                const cx<R> sa = yb[r] + bup + lane_prev(yb[r]);   // B(n), B(n - e1), B(n - e2)
+                const cx<R> sb = ya[r] + adn + lane_next(ya[r]);   // A(m), A(m + e1), A(m + e2)
+                bup = yb[r];
+                ya[r] = {fmar(ck, sa.re, va[r].re), fmar(ck, sa.im, va[r].im)};
+                yb[r] = {fmar(ck, sb.re, vb[r].re), fmar(ck, sb.im, vb[r].im)};
+            }
+        }
+        if constexpr (!kEpiEarly) {
+            fetch_epi();
+            early_epi();
+        }
+        if (out_lane) {
+#pragma unroll
+            for (int r = 0; r < RM; ++r)
+                if (r < nr) {
+                    epi.store(rhs, t, (r0 + r) * L + n2, scale(emu, ya[r]), ea[r], T, sc, acc);
+                    epi.store(rhs, t, LL + (r0 + r) * L + n2, scale(emu, yb[r]), eb[r], T, sc, acc);
+                }
+        }
+    }
+    if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
+}
+
 // One workgroup per (right-hand side, slice) for slices larger than LDS whose single
 // sublattice fits (FP32 at L = 102: 84 KB of the slice's 167 KB).  Sublattice A is
 // transformed forward in LDS and its spectrum parked in registers (each thread keeps

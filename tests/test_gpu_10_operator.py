@@ -69,13 +69,14 @@ def test_apply_diff_workload_fp64():
     assert_close_elementwise(to_np(hub.apply_Mdag(to_dev(phi), to_dev(v))), op.apply_Mdag(phi, v), RTOL64, "Mdag")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_apply_precision_workload(prec):
-    """L = 51, Nt = 128: the full operator against the oracle's Krylov-exp route."""
+@pytest.mark.parametrize("prec,path", [("fp64", "auto"), ("fp32", "auto"), ("fp32", "fused")])
+def test_apply_precision_workload(prec, path):
+    """L = 51, Nt = 128: the full operator against the oracle's Krylov-exp route (FP32: the
+    default Taylor-stencil kernel and the transform kernels of the forced fused path)."""
     w = PREC
-    print(f"[case] apply {prec} {w.name}", flush=True)
+    print(f"[case] apply {prec} {w.name} path={path}", flush=True)
     phi, v = draw_inputs(w, seed=14)
-    hub = _hub(w)
+    hub = _hub(w, path=path)
     op = oracle_op(w, mode="expm")
     if prec == "fp64":
         got = to_np(hub.apply_M(to_dev(phi), to_dev(v)))
@@ -92,15 +93,18 @@ def test_apply_precision_workload(prec):
         assert_close_elementwise(got, ref, RTOL32, "Mdag32")
 
 
+@pytest.mark.parametrize("path", ["auto", "fused"])
 @pytest.mark.parametrize("nrhs", [1, 2])
-def test_apply_fp32_both_operators_precision_workload(nrhs):
-    """L = 51, N_t = 128 in FP32: M and M^dag, every entry, with one right-hand side (128 slices:
-    two workgroups per slice, each writing one sublattice) and two (256 slices: one workgroup
-    per slice), against the oracle applied to the same FP32-rounded inputs."""
+def test_apply_fp32_both_operators_precision_workload(nrhs, path):
+    """L = 51, N_t = 128 in FP32: M and M^dag, every entry, with one and two right-hand sides,
+    against the oracle applied to the same FP32-rounded inputs.  path auto: the Taylor-stencil
+    kernel (two workgroups per slice, each writing half the columns); fused: the transform
+    kernels (one right-hand side, 128 slices: two workgroups per slice, each writing one
+    sublattice; two, 256 slices: one workgroup per slice)."""
     w = PREC
-    print(f"[case] apply fp32 M and Mdag {w.name} nrhs={nrhs}", flush=True)
+    print(f"[case] apply fp32 M and Mdag {w.name} nrhs={nrhs} path={path}", flush=True)
     phi, v = draw_inputs(w, seed=24, nrhs=nrhs)
-    hub = _hub(w, nrhs=nrhs)
+    hub = _hub(w, nrhs=nrhs, path=path)
     op = oracle_op(w, mode="expm")
     p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
     p64, v64 = p32.astype(np.float64), v32.astype(np.complex128)
@@ -213,7 +217,7 @@ def test_half_and_whole_slice_kernels_agree(prec):
     w = PREC
     print(f"[case] paired vs single {prec} {w.name}", flush=True)
     phi, v = draw_inputs(w, seed=18, nrhs=2)
-    hub = _hub(w, nrhs=2)
+    hub = _hub(w, nrhs=2, path="fused")
     op = oracle_op(w, mode="expm")
     if prec == "fp64":
         P, V = to_dev(phi), to_dev(v)
@@ -443,18 +447,21 @@ def test_context_manager_releases_the_context():
     assert torch.isfinite(ref.real).all()
 
 
-@pytest.mark.parametrize("L,Nt,nrhs", [(51, 255, 1), (51, 127, 2), (51, 60, 4), (51, 1, 1), (51, 3, 3),
-                                       (102, 5, 3), (102, 1, 2)])
-def test_production_lengths_at_odd_shapes(L, Nt, nrhs):
+@pytest.mark.parametrize("L,Nt,nrhs,path", [(51, 255, 1, "auto"), (51, 127, 2, "auto"), (51, 60, 4, "auto"),
+                                            (51, 1, 1, "auto"), (51, 3, 3, "auto"), (51, 255, 1, "fused"),
+                                            (51, 127, 2, "fused"), (51, 60, 4, "fused"), (51, 1, 1, "fused"),
+                                            (51, 3, 3, "fused"), (102, 5, 3, "auto"), (102, 1, 2, "auto")])
+def test_production_lengths_at_odd_shapes(L, Nt, nrhs, path):
     """The compile-time L = 51 and L = 102 kernels on both sides of the two-workgroup switch
     (fewer than 256 slices), with several right-hand sides, a single slice and odd N_t: M, M^dag,
-    FP32 M and M^dag and the force on sampled slices against the oracle's Krylov route."""
+    FP32 M and M^dag and the force on sampled slices against the oracle's Krylov route (at
+    L = 51 FP32 both the Taylor-stencil kernel of the default path and the transform kernels)."""
     from paper_2210_06874_amd import Hubbard
-    print(f"[case] production length L={L} Nt={Nt} nrhs={nrhs}", flush=True)
+    print(f"[case] production length L={L} Nt={Nt} nrhs={nrhs} path={path}", flush=True)
     w = Lattice(f"L{L}_Nt{Nt}", L, Nt, 0.0625 * Nt, 3.9, nrhs=nrhs)
     phi, v = draw_inputs(w, seed=L + Nt, nrhs=nrhs)
     op = oracle_op(w, mode="expm")
-    hub = Hubbard(L, Nt, w.beta, w.kappa, nrhs_max=nrhs)
+    hub = Hubbard(L, Nt, w.beta, w.kappa, nrhs_max=nrhs, path=path)
     P, V = to_dev(phi), to_dev(v)
     M64, D64 = to_np(hub.apply_M(P, V)), to_np(hub.apply_Mdag(P, V))
     p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
@@ -475,3 +482,31 @@ def test_production_lengths_at_odd_shapes(L, Nt, nrhs):
                                  RTOL32, f"Mdag32 slice {t}")
         gref = (-2.0 * Btn * (np.exp(1j * phi[t])[None] * v[:, t] * np.conj(wv)).imag).sum(axis=0)
         assert_close_elementwise(g[t], gref, 1e-11, f"force slice {t}")
+
+
+@pytest.mark.parametrize("beta,Nt,kappa,mu", [(8.0, 128, 1.0, 0.0), (8.0, 128, -1.0, 0.3), (8.0, 96, 1.0, -0.4),
+                                             (8.0, 32, 1.0, 0.0), (2.0, 4, -1.0, 0.2)])
+def test_taylor_stencil_and_transform_kernels_at_L51(beta, Nt, kappa, mu):
+    """FP32 at L = 51: the default path applies E by its degree-6 Taylor polynomial while
+    x = 3|delta kappa| <= 0.25 (here x = 0.1875 with either sign of kappa, 0.25 exactly at
+    Nt = 96, where the remainder bound is largest) and by the transforms above it (x = 0.75,
+    1.5), and the forced fused path always by the transforms.  Every entry of M and M^dag of
+    both, with mu != 0 (e^{delta mu} scales E), within 1e-6 of the largest entry of the
+    oracle's result on the same FP32-rounded inputs: FP32 rounding (random shapes show at most
+    3e-7), so the polynomial's truncation (at most 1.3e-8) is invisible and a wrong choice of
+    kernel (x = 0.75 by degree 6: about 6e-5) is not."""
+    from paper_2210_06874_amd import Hubbard
+    L = 51
+    print(f"[case] Taylor vs transform L={L} Nt={Nt} beta={beta} kappa={kappa} mu={mu}", flush=True)
+    w = Lattice(f"L{L}_Nt{Nt}", L, Nt, beta, 3.85, kappa=kappa)
+    phi, v = draw_inputs(w, seed=Nt + 5, nrhs=1)
+    p32, v32 = phi.astype(np.float32), v.astype(np.complex64)
+    p64, v64 = p32.astype(np.float64), v32.astype(np.complex128)
+    op = O.HubbardOperator(L, Nt, beta, kappa, mu=mu, mode="expm")
+    refM, refD = op.apply_M(p64, v64), op.apply_Mdag(p64, v64)
+    for path in ("auto", "fused"):
+        hub = Hubbard(L, Nt, beta, kappa, path=path, mu=mu)
+        P, V = to_dev(p32), to_dev(v32)
+        eM = assert_close_elementwise(to_np(hub.apply_M_c64(P, V)), refM, 1e-6, f"M32 {path}")
+        eD = assert_close_elementwise(to_np(hub.apply_Mdag_c64(P, V)), refD, 1e-6, f"Mdag32 {path}")
+        print(f"    {path}: M {eM:.2e} Mdag {eD:.2e}", flush=True)
