@@ -289,9 +289,12 @@ hub_status hub_log_det(hub_ctx* ctx, const double* phi, double* out_dev, void* s
  * one-sublattice-at-a-time kernel (exponential form, L = 102) run as one cooperative launch per
  * block of iterations (all right-hand sides in one launch; every workgroup loops over
  * (right-hand side, slice) items, with grid barriers between the M^dag and M phases), provided
- * the device holds the whole grid at once, else as two launches per iteration; the result is the
- * same bit for bit.  persistent = 0 (the default, measured faster on MI355X): always two
- * launches per iteration.
+ * the device holds the whole grid at once, else as two launches per iteration of that kernel;
+ * the result is the same bit for bit.  persistent = 2: always two launches per iteration of that
+ * same kernel (what the persistent launch reproduces).  With 1 or 2 every FP32 operator of an
+ * L = 102 context uses the sublattice kernel.  persistent = 0 (the default): two launches per
+ * iteration with the context's fastest FP32 kernels (at L = 102 and 3 |delta kappa| <= 0.25 the
+ * Taylor-polynomial stencil, see hub_apply_M_c64), measured faster on MI355X than both.
  * barrier_spin_limit > 0 bounds every wait at a grid barrier to that many polls (0 restores the
  * default, 2^24 polls, seconds); a wait that runs out makes every workgroup leave the launch and
  * hub_cg_solve return HUB_ERR_DEVICE with x undefined. */

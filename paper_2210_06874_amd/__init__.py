@@ -260,10 +260,13 @@ class Hubbard:
         res.persistent_launches = info[0].persistent_launches
         return res
 
-    def set_cg_launch(self, persistent: bool = False, barrier_spin_limit: int = 0) -> None:
-        """hub_set_cg_launch: persistent CG launches where they apply, or two launches per iteration
-        (the default); barrier_spin_limit > 0 bounds each grid-barrier wait (polls)."""
-        _lib.check(self.lib.hub_set_cg_launch(self._h, 1 if persistent else 0, int(barrier_spin_limit)))
+    def set_cg_launch(self, persistent: bool = False, barrier_spin_limit: int = 0, sublattice: bool = False) -> None:
+        """hub_set_cg_launch: persistent CG launches where they apply (mode 1), two launches per
+        iteration of the sublattice kernel the persistent launch is built from (sublattice=True,
+        mode 2), or two launches per iteration with the fastest kernels (the default, mode 0);
+        barrier_spin_limit > 0 bounds each grid-barrier wait (polls)."""
+        mode = 1 if persistent else (2 if sublattice else 0)
+        _lib.check(self.lib.hub_set_cg_launch(self._h, mode, int(barrier_spin_limit)))
 
     def force(self, phi, x, out=None):
         """dS/dphi (float64 [Nt, V]) of S = chi^dag (M M^dag)^{-1} chi from the solutions x."""

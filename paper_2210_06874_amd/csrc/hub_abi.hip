@@ -18,12 +18,16 @@ constexpr int kThreads51 = 512;     // workgroup size of the L = 51 kernels
 // the minimum-norm choice of the Omelyan-Mryglod-Folk second-order integrator
 constexpr double kOmelyanLambda = 0.1931833275037836;
 constexpr int kHalfBelow = 256;     // two workgroups per slice below this many slices
-// FP32 operators at L = 51 by the degree-6 Taylor polynomial of exp(delta kappa K) while
+// FP32 operators at L = 51 and 102 by the degree-6 Taylor polynomial of exp(delta kappa K) while
 // x = 3 |delta kappa| <= 0.25: its remainder, at most x^7/7! e^x, is then under 1.3e-8, a fifth
-// of FP32's unit roundoff (larger steps, and every FP64 operator, take the FFT kernels)
+// of FP32's unit roundoff (larger steps, and every FP64 operator, take the FFT kernels).  Two
+// workgroups per slice split the 51 columns, four the 102 (each range plus its halos fits 32
+// lanes); 512 threads: 16 strips of 3-4 rows (L = 51; 768 and 1024 measured slower in CG) or
+// 6-7 rows (L = 102)
 constexpr double kTaylorMaxX = 0.25;
 constexpr int kTaylorDeg = 6;
-constexpr int kThreadsTaylor = 512;   // 16 strips (half waves) of 3-4 rows; 768 and 1024 measured slower in CG
+constexpr int kThreadsTaylor = 512;
+constexpr int taylor_split(int L) { return L == 51 ? 2 : 4; }
 
 thread_local char g_err[512] = "";
 
@@ -128,7 +132,7 @@ void allow_lds(K kern, size_t bytes) {
 
 // Which operator kernel runs for nrhs right-hand sides, and how many reduction slots
 // (blocks per right-hand side) it has.
-enum class OpKind { Generic, Whole51, Half51, Taylor51, Split, Linear, Sub102 };
+enum class OpKind { Generic, Whole51, Half51, Taylor, Split, Linear, Sub102 };
 
 // Workgroup size of the sublattice-at-a-time kernel.  Its 84 KB tile allows one workgroup
 // per compute unit, so the waves per CU are the workgroup's own: twelve (three per SIMD)
@@ -156,11 +160,15 @@ int lin_nch(const hub_ctx* c, int nrhs) {
 template <typename R>
 OpKind op_kind(const hub_ctx* c, int nrhs) {
     if (c->form == HUB_FORM_LINEAR) return OpKind::Linear;
+    // FP32 at L = 51 or 102 with small delta kappa: the Taylor stencil; the persistent CG launch
+    // is built from the L = 102 sublattice kernel, so with its modes (1, 2) on those operators stay
+    // that kernel
+    if (c->specialized && c->taylor && sizeof(R) == sizeof(float) && !(c->L == 102 && c->persist_mode))
+        return OpKind::Taylor;
     if (c->path == HUB_PATH_SPLIT) {
         if (!c->split_forced && c->specialized && c->L == 102 && sizeof(R) == sizeof(float)) return OpKind::Sub102;
         return OpKind::Split;
     }
-    if (c->L == 51 && c->specialized && c->taylor && sizeof(R) == sizeof(float)) return OpKind::Taylor51;
     if (c->L == 51 && c->specialized) return nrhs * c->Nt < kHalfBelow ? OpKind::Half51 : OpKind::Whole51;
     return OpKind::Generic;
 }
@@ -168,8 +176,8 @@ OpKind op_kind(const hub_ctx* c, int nrhs) {
 template <typename R>
 int op_slots(const hub_ctx* c, int nrhs) {
     switch (op_kind<R>(c, nrhs)) {
-        case OpKind::Half51:
-        case OpKind::Taylor51: return 2 * c->Nt;
+        case OpKind::Half51: return 2 * c->Nt;
+        case OpKind::Taylor: return taylor_split(c->L) * c->Nt;
         case OpKind::Split: return 2 * c->Nt * split_geom(c->L).nrb;
         case OpKind::Linear: return c->Nt * lin_nch(c, nrhs);
         default: return c->Nt;
@@ -225,12 +233,19 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
             hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
             return launch_check("k_fused_ct<51, half>");
         }
-        case OpKind::Taylor51: {
+        case OpKind::Taylor: {
             if constexpr (sizeof(R) == sizeof(float)) {
-                auto kern = k_taylor<R, 51, kThreadsTaylor, kTaylorDeg, Src, Epi, Ctl>;
-                hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreadsTaylor), 0, st, T,
-                                   (R)(c->delta * c->kappa), (R)std::exp(c->delta * c->mu), src, epi, ctl);
-                return launch_check("k_taylor<51>");
+                const R dk = (R)(c->delta * c->kappa), emu = (R)std::exp(c->delta * c->mu);
+                if (c->L == 51) {
+                    auto kern = k_taylor<R, 51, kThreadsTaylor, kTaylorDeg, taylor_split(51), Src, Epi, Ctl>;
+                    hipLaunchKernelGGL(kern, dim3(taylor_split(51) * nrhs * c->Nt), dim3(kThreadsTaylor), 0, st, T,
+                                       dk, emu, src, epi, ctl);
+                    return launch_check("k_taylor<51>");
+                }
+                auto kern = k_taylor<R, 102, kThreadsTaylor, kTaylorDeg, taylor_split(102), Src, Epi, Ctl>;
+                hipLaunchKernelGGL(kern, dim3(taylor_split(102) * nrhs * c->Nt), dim3(kThreadsTaylor), 0, st, T,
+                                   dk, emu, src, epi, ctl);
+                return launch_check("k_taylor<102>");
             }
             return fail(HUB_ERR_ARG, "internal: the Taylor kernel is FP32 only");
         }
@@ -451,7 +466,7 @@ hub_status ensure_cg_workspace(hub_ctx* c) {
 hub_status try_persistent(hub_ctx* c, int nrhs, long long from, long long n, const PersistArgs<float>& base,
                           hipStream_t st, bool* done) {
     *done = false;
-    if (!c->persist_mode || !c->persist_ok || c->form != HUB_FORM_EXP || op_kind<float>(c, nrhs) != OpKind::Sub102)
+    if (c->persist_mode != 1 || !c->persist_ok || c->form != HUB_FORM_EXP || op_kind<float>(c, nrhs) != OpKind::Sub102)
         return HUB_OK;
     auto kern = k_cg_persist_sub<float, 102, kThreadsSub>;
     const size_t lds = (size_t)(c->L * c->L + c->L) * sizeof(cx<float>);
@@ -782,7 +797,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     c->path = (prm->path == HUB_PATH_SPLIT || (prm->path == HUB_PATH_AUTO && !fits)) ? HUB_PATH_SPLIT
                                                                                       : HUB_PATH_FUSED;
     c->split_forced = prm->path == HUB_PATH_SPLIT;
-    c->taylor = !lin && prm->path == HUB_PATH_AUTO && c->path == HUB_PATH_FUSED && c->L == 51 &&
+    c->taylor = !lin && prm->path == HUB_PATH_AUTO && (c->L == 51 || c->L == 102) &&
                 3.0 * std::fabs(c->delta * c->kappa) <= kTaylorMaxX;
 
     std::vector<double> roots, etab;
@@ -1150,7 +1165,7 @@ hub_status hub_trajectory(hub_ctx* c, double* phi, const double* pi0, const void
 
 hub_status hub_set_cg_launch(hub_ctx* c, int32_t persistent, int64_t barrier_spin_limit) {
     if (!c) return fail(HUB_ERR_ARG, "ctx is NULL");
-    if (persistent != 0 && persistent != 1) return fail(HUB_ERR_ARG, "persistent must be 0 or 1");
+    if (persistent < 0 || persistent > 2) return fail(HUB_ERR_ARG, "persistent must be 0, 1 or 2");
     if (barrier_spin_limit < 0) return fail(HUB_ERR_ARG, "barrier_spin_limit must be >= 0");
     c->persist_mode = persistent;
     c->persist_spin = barrier_spin_limit > 0 ? (long long)barrier_spin_limit : (1LL << 24);

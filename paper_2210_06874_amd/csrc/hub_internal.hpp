@@ -43,7 +43,7 @@ struct hub_ctx {
     int form = HUB_FORM_EXP;
     bool specialized = true;         // use a compile-time-L kernel when one exists
     bool split_forced = false;       // HUB_PATH_SPLIT requested: no fused kernel of any kind
-    bool taylor = false;             // FP32 operators by the Taylor-stencil kernel (HUB_PATH_AUTO, L = 51)
+    bool taylor = false;             // FP32 operators by the Taylor-stencil kernel (HUB_PATH_AUTO, L = 51, 102)
     int lds_fused64 = 0, lds_fused32 = 0;
     int max_lds = 0;
     hub::FftPlan plan{};

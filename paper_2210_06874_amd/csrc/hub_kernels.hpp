@@ -1068,9 +1068,10 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
 // at most x^{DEG+1}/(DEG+1)! e^x with x = 3 |delta kappa| (the largest eigenvalue of K is 3);
 // the host uses this kernel only where that is far below the precision's rounding.
 //
-// Two workgroups per slice split the columns n2: workgroup h writes columns [h*(L/2), ...) and
-// carries H = ceil(DEG/2) halo columns on each side, since each pair of sweeps widens a
-// site's dependence by one column each way (A(n) reaches B(n - e2), B(m) reaches A(m + e2)).
+// NSPLIT workgroups per slice split the columns n2: workgroup h writes columns
+// [h L / NSPLIT, (h + 1) L / NSPLIT) and carries H = ceil(DEG/2) halo columns on each side,
+// since each pair of sweeps widens a site's dependence by one column each way (A(n) reaches
+// B(n - e2), B(m) reaches A(m + e2)).
 // Lanes run along n2 (32 lanes per strip when the columns and halos fit, so a strip is half a
 // wave, else 64; a site's n2 neighbours are the adjacent lanes, fetched with wave-wide DPP
 // shifts, and the lanes at a strip's two edges receive another strip's values or 0, which only
@@ -1078,10 +1079,10 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
 // strips) the FFT kernels measured faster.  Rows n1 (periodic, all
 // L of them) are split into NT/32 strips of at most RMAX rows held in registers; the row above
 // and below a strip cross strips through LDS once per sweep.
-template <int L, int NT, int DEG>
+template <int L, int NT, int DEG, int NSPLIT>
 struct TayGeom {
     static constexpr int H = (DEG + 1) / 2;
-    static constexpr int W = L - L / 2 + 2 * H;          // widest column range with its halos
+    static constexpr int W = (L + NSPLIT - 1) / NSPLIT + 2 * H;   // widest column range with its halos
     static constexpr int LPS = W <= 32 ? 32 : 64;        // lanes (columns) per strip
     static constexpr int NSTRIP = NT / LPS;
     static constexpr int RMAX = (L + NSTRIP - 1) / NSTRIP;
@@ -1104,23 +1105,23 @@ __device__ __forceinline__ cx<float> lane_next(cx<float> v) {
     return {lane_shift<kDppWaveShl1>(v.re), lane_shift<kDppWaveShl1>(v.im)};
 }
 
-template <typename R, int L, int NT, int DEG, class Src, class Epi, class Ctl>
+template <typename R, int L, int NT, int DEG, int NSPLIT, class Src, class Epi, class Ctl>
 __global__ void __launch_bounds__(NT)
 k_taylor(const OpTab<R> T, const R dk, const R emu, const Src src, const Epi epi, const Ctl ctl) {
     static_assert(sizeof(R) == sizeof(float), "FP32 only: in FP64 the FFT kernels measured faster");
-    using G = TayGeom<L, NT, DEG>;
+    using G = TayGeom<L, NT, DEG, NSPLIT>;
     constexpr int LL = L * L, RM = G::RMAX, NS = G::NSTRIP;
     __shared__ cx<R> edgeA[2][NS][G::LPS];               // first row's A of each strip, per sweep parity
     __shared__ cx<R> edgeB[2][NS][G::LPS];               // last row's B
     __shared__ double red_lds[64];
     const int u = xcd_linear(blockIdx.x, gridDim.x);
-    const int q = u >> 1, h = u & 1;
+    const int q = u / NSPLIT, h = u - q * NSPLIT;
     const int rhs = q / T.Nt, t = q - rhs * T.Nt;
-    const int slot = 2 * t + h;
+    const int slot = NSPLIT * t + h;
     const int tid = threadIdx.x;
     const int s = tid / G::LPS, j = tid - s * G::LPS;
     const int r0 = s * L / NS, nr = (s + 1) * L / NS - r0;
-    const int c0 = h * (L / 2), ncol = h ? L - L / 2 : L / 2;
+    const int c0 = h * L / NSPLIT, ncol = (h + 1) * L / NSPLIT - c0;
     const int n2 = (c0 - G::H + j + L) % L;
     const bool out_lane = j >= G::H && j < G::H + ncol;
     // every global load before the block's CG scalars (as in k_fused_ct): partials, source

@@ -155,14 +155,20 @@ def _stress_slices(op, phi, v, slices, dagger):
     return out
 
 
+@pytest.mark.parametrize("kernel", ["default", "sublattice"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_apply_stress_workload_sampled(prec):
-    """L = 102, Nt = 192, 4 right-hand sides in one call (split path): sampled slices,
-    including both wrap slices, against the oracle."""
+def test_apply_stress_workload_sampled(prec, kernel):
+    """L = 102, Nt = 192, 4 right-hand sides in one call: sampled slices, including both wrap
+    slices, against the oracle (FP64: split path; FP32: the default Taylor stencil and the
+    sublattice kernel)."""
+    if prec == "fp64" and kernel == "sublattice":
+        pytest.skip("the sublattice kernel is FP32 only")
     w = STRESS
-    print(f"[case] apply {prec} {w.name}", flush=True)
+    print(f"[case] apply {prec} {w.name} {kernel}", flush=True)
     phi, v = draw_inputs(w, seed=15)
     hub = _hub(w, nrhs=4)
+    if kernel == "sublattice":
+        hub.set_cg_launch(sublattice=True)
     op = oracle_op(w, mode="expm")
     slices = [0, 1, 77, w.Nt - 1]
     if prec == "fp32":
@@ -253,18 +259,25 @@ def test_apply_with_chemical_potential(mu):
 
 @pytest.mark.parametrize("dag", [False, True])
 def test_sublattice_and_split_kernels_agree(dag):
-    """L = 102 in FP32: the one-workgroup-per-slice kernel that keeps one sublattice's
-    spectrum in registers against the three-kernel split path (both against the oracle on
-    sampled slices in test_apply_stress_workload_sampled)."""
+    """L = 102 in FP32: the default Taylor-stencil kernel, the one-workgroup-per-slice kernel that
+    keeps one sublattice's spectrum in registers (selected by the sublattice launch mode) and the
+    three-kernel split path agree (all against the oracle on sampled slices in
+    test_apply_stress_workload_sampled)."""
     w = STRESS
-    print(f"[case] sublattice vs split dag={dag}", flush=True)
+    print(f"[case] Taylor vs sublattice vs split dag={dag}", flush=True)
     phi, v = draw_inputs(w, seed=18, nrhs=2)
     P32, V32 = to_dev(phi.astype(np.float32)), to_dev(v.astype(np.complex64))
     a = _hub(w, "auto", nrhs=2)
     b = _hub(w, "split", nrhs=2)
     fa = a.apply_Mdag_c64 if dag else a.apply_M_c64
     fb = b.apply_Mdag_c64 if dag else b.apply_M_c64
-    assert_close_elementwise(to_np(fa(P32, V32)), to_np(fb(P32, V32)), 4e-6, "sub vs split")
+    taylor = to_np(fa(P32, V32))
+    a.set_cg_launch(sublattice=True)
+    sub = to_np(fa(P32, V32))
+    a.set_cg_launch()
+    split = to_np(fb(P32, V32))
+    assert_close_elementwise(taylor, split, 4e-6, "Taylor vs split")
+    assert_close_elementwise(sub, split, 4e-6, "sub vs split")
 
 
 @pytest.mark.parametrize("form", ["exp", "linear"])

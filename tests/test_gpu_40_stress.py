@@ -62,11 +62,13 @@ def test_stress_batched_equals_single(stress, persistent):
 
 def test_stress_persistent_equals_two_kernel_iterations(stress):
     """The persistent launch (grid barriers between the M^dag and M phases) and two launches per
-    iteration give the same solution bit for bit, with the same iteration counts."""
+    iteration of the same sublattice kernel give the same solution bit for bit, with the same
+    iteration counts."""
     w, hub, op, phi, rho, P, chi = stress
     print("[case] stress persistent vs two-kernel", flush=True)
-    two = hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=20000)
     try:
+        hub.set_cg_launch(sublattice=True)
+        two = hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=20000)
         hub.set_cg_launch(persistent=True)
         per = hub.cg_solve(P, chi, tol=1e-10, prec="mixed", max_iter=20000)
     finally:
