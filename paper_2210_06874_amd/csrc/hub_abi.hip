@@ -760,7 +760,8 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     const long long N = 2LL * prm->L * prm->L * prm->Nt;
     if ((long long)prm->nrhs_max * N >= (1LL << 40)) return fail(HUB_ERR_ARG, "problem too large");
     // every launch grid must fit a 32-bit block index: at most 2 * max(nrb, ncb) blocks per
-    // slice for the transforms, at most max(Nt, 1024) blocks per right-hand side for the stencil
+    // slice for the transforms (at least the Taylor stencil's 2 at L = 51 and 4 at L = 102), at
+    // most max(Nt, 1024) blocks per right-hand side for the linear stencil
     const SplitGeom g = split_geom(prm->L);
     const long long grid_per_rhs = lin ? std::max<long long>(prm->Nt, 1024)
                                        : 2LL * prm->Nt * std::max(g.nrb, g.ncb);

@@ -1139,12 +1139,15 @@ k_taylor(const OpTab<R> T, const R dk, const R emu, const Src src, const Epi epi
     // the sweeps), else fetched after the sweeps
     constexpr bool kEpiEarly = sizeof(typename Epi::Pre) * 2 * RM <= 256;
     typename Epi::Pre ea[RM], eb[RM];
+    // only the lanes and rows that write load them (a halo lane or a strip's missing last row
+    // never uses its operands; the masked loads move no data)
     auto fetch_epi = [&]() {
 #pragma unroll
         for (int r = 0; r < RM; ++r) {
-            const int n1 = r0 + min(r, nr - 1);
-            ea[r] = epi.fetch(rhs, t, n1 * L + n2, T);
-            eb[r] = epi.fetch(rhs, t, LL + n1 * L + n2, T);
+            if (out_lane && r < nr) {
+                ea[r] = epi.fetch(rhs, t, (r0 + r) * L + n2, T);
+                eb[r] = epi.fetch(rhs, t, LL + (r0 + r) * L + n2, T);
+            }
         }
     };
     if constexpr (kEpiEarly) fetch_epi();
