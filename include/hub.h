@@ -79,7 +79,7 @@ typedef enum { HUB_PREC_FP64 = 0, HUB_PREC_MIXED = 1 } hub_prec;
 
 /* Which kernel layout applies E: AUTO picks the fused one-slice-per-workgroup
  * kernel when a slice fits in LDS, else the three-kernel split path, and at L = 51 with
- * 3 |delta kappa| <= 0.25 the Taylor-polynomial stencil for the FP32 operators (see
+ * 3 |delta kappa| <= 0.25 the polynomial stencil for the FP32 operators (see
  * hub_apply_M_c64).  FUSED and SPLIT force one (FUSED fails with HUB_ERR_ARG when the slice
  * does not fit); both apply E through the transforms in both precisions. */
 typedef enum { HUB_PATH_AUTO = 0, HUB_PATH_FUSED = 1, HUB_PATH_SPLIT = 2 } hub_path;
@@ -148,9 +148,10 @@ hub_status hub_apply_Mdag(hub_ctx* ctx, const double* phi, const void* in, void*
 /* FP32 variants of the two operators (complex64 vectors, float phi): the kernels
  * that the mixed-precision CG iterates with.  With HUB_PATH_AUTO at L = 51 and
  * 3 |delta kappa| <= 0.25 they apply E = e^{delta mu} exp(delta kappa K) (Sec. 2, eq.
- * "ferm_op") as its degree-6 Taylor polynomial in delta kappa K, whose truncation is at most
- * 1.3e-8 relative (K's spectrum lies in [-3, 3]), below FP32 rounding; otherwise, and in
- * every FP64 entry point, through the per-slice transforms. */
+ * "ferm_op") as e^{delta mu} p(delta kappa K), p the degree-5 Chebyshev interpolant of e^z on
+ * [-3|delta kappa|, 3|delta kappa|] (K's spectrum lies in [-3, 3]), an error of at most 1.1e-8
+ * relative, below FP32 rounding; otherwise, and in every FP64 entry point, through the
+ * per-slice transforms. */
 hub_status hub_apply_M_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,
                            int32_t nrhs, void* stream);
 hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,
@@ -294,7 +295,7 @@ hub_status hub_log_det(hub_ctx* ctx, const double* phi, double* out_dev, void* s
  * same kernel (what the persistent launch reproduces).  With 1 or 2 every FP32 operator of an
  * L = 102 context uses the sublattice kernel.  persistent = 0 (the default): two launches per
  * iteration with the context's fastest FP32 kernels (at L = 102 and 3 |delta kappa| <= 0.25 the
- * Taylor-polynomial stencil, see hub_apply_M_c64), measured faster on MI355X than both.
+ * polynomial stencil, see hub_apply_M_c64), measured faster on MI355X than both.
  * barrier_spin_limit > 0 bounds every wait at a grid barrier to that many polls (0 restores the
  * default, 2^24 polls, seconds); a wait that runs out makes every workgroup leave the launch and
  * hub_cg_solve return HUB_ERR_DEVICE with x undefined. */

@@ -18,16 +18,19 @@ constexpr int kThreads51 = 512;     // workgroup size of the L = 51 kernels
 // the minimum-norm choice of the Omelyan-Mryglod-Folk second-order integrator
 constexpr double kOmelyanLambda = 0.1931833275037836;
 constexpr int kHalfBelow = 256;     // two workgroups per slice below this many slices
-// FP32 operators at L = 51 and 102 by the degree-6 Taylor polynomial of exp(delta kappa K) while
-// x = 3 |delta kappa| <= 0.25: its remainder, at most x^7/7! e^x, is then under 1.3e-8, a fifth
-// of FP32's unit roundoff (larger steps, and every FP64 operator, take the FFT kernels).  Two
+// FP32 operators at L = 51 and 102 by a degree-5 polynomial of delta kappa K (exp_poly_ratios: the
+// Chebyshev interpolant of e^z on [-x, x], x = 3 |delta kappa|) while x <= 0.25 and its error
+// bound is at most kPolyTol (1.1e-8 at x = 0.25, 1.9e-9 at the paper's x = 0.1875), a sixth of
+// FP32's unit roundoff or less; larger steps, and every FP64 operator, take the FFT kernels.  The
+// degree-6 Taylor polynomial reaches the same accuracy with one sweep more (5-8 % slower).  Two
 // workgroups per slice split the 51 columns, four the 102 (each range plus its halos fits 32
 // lanes); 512 threads: 16 strips of 3-4 rows (L = 51; 768 and 1024 measured slower in CG) or
 // 6-7 rows (L = 102)
-constexpr double kTaylorMaxX = 0.25;
-constexpr int kTaylorDeg = 6;
-constexpr int kThreadsTaylor = 512;
-constexpr int taylor_split(int L) { return L == 51 ? 2 : 4; }
+constexpr double kPolyMaxX = 0.25;
+constexpr int kPolyDeg = 5;
+constexpr double kPolyTol = 2e-8;
+constexpr int kThreadsPoly = 512;
+constexpr int poly_split(int L) { return L == 51 ? 2 : 4; }
 
 thread_local char g_err[512] = "";
 
@@ -132,7 +135,7 @@ void allow_lds(K kern, size_t bytes) {
 
 // Which operator kernel runs for nrhs right-hand sides, and how many reduction slots
 // (blocks per right-hand side) it has.
-enum class OpKind { Generic, Whole51, Half51, Taylor, Split, Linear, Sub102 };
+enum class OpKind { Generic, Whole51, Half51, Poly, Split, Linear, Sub102 };
 
 // Workgroup size of the sublattice-at-a-time kernel.  Its 84 KB tile allows one workgroup
 // per compute unit, so the waves per CU are the workgroup's own: twelve (three per SIMD)
@@ -160,11 +163,11 @@ int lin_nch(const hub_ctx* c, int nrhs) {
 template <typename R>
 OpKind op_kind(const hub_ctx* c, int nrhs) {
     if (c->form == HUB_FORM_LINEAR) return OpKind::Linear;
-    // FP32 at L = 51 or 102 with small delta kappa: the Taylor stencil; the persistent CG launch
+    // FP32 at L = 51 or 102 with small delta kappa: the polynomial stencil; the persistent CG launch
     // is built from the L = 102 sublattice kernel, so with its modes (1, 2) on those operators stay
     // that kernel
-    if (c->specialized && c->taylor && sizeof(R) == sizeof(float) && !(c->L == 102 && c->persist_mode))
-        return OpKind::Taylor;
+    if (c->specialized && c->poly && sizeof(R) == sizeof(float) && !(c->L == 102 && c->persist_mode))
+        return OpKind::Poly;
     if (c->path == HUB_PATH_SPLIT) {
         if (!c->split_forced && c->specialized && c->L == 102 && sizeof(R) == sizeof(float)) return OpKind::Sub102;
         return OpKind::Split;
@@ -177,7 +180,7 @@ template <typename R>
 int op_slots(const hub_ctx* c, int nrhs) {
     switch (op_kind<R>(c, nrhs)) {
         case OpKind::Half51: return 2 * c->Nt;
-        case OpKind::Taylor: return taylor_split(c->L) * c->Nt;
+        case OpKind::Poly: return poly_split(c->L) * c->Nt;
         case OpKind::Split: return 2 * c->Nt * split_geom(c->L).nrb;
         case OpKind::Linear: return c->Nt * lin_nch(c, nrhs);
         default: return c->Nt;
@@ -233,21 +236,23 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
             hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
             return launch_check("k_fused_ct<51, half>");
         }
-        case OpKind::Taylor: {
+        case OpKind::Poly: {
             if constexpr (sizeof(R) == sizeof(float)) {
-                const R dk = (R)(c->delta * c->kappa), emu = (R)std::exp(c->delta * c->mu);
+                PolyCoef<R> pc{};
+                pc.scale = (R)(std::exp(c->delta * c->mu) * c->poly_a0);
+                for (int k = 1; k <= kPolyDeg; ++k) pc.c[k] = (R)(c->delta * c->kappa * c->poly_ratio[k]);
                 if (c->L == 51) {
-                    auto kern = k_taylor<R, 51, kThreadsTaylor, kTaylorDeg, taylor_split(51), Src, Epi, Ctl>;
-                    hipLaunchKernelGGL(kern, dim3(taylor_split(51) * nrhs * c->Nt), dim3(kThreadsTaylor), 0, st, T,
-                                       dk, emu, src, epi, ctl);
-                    return launch_check("k_taylor<51>");
+                    auto kern = k_exp_poly<R, 51, kThreadsPoly, kPolyDeg, poly_split(51), Src, Epi, Ctl>;
+                    hipLaunchKernelGGL(kern, dim3(poly_split(51) * nrhs * c->Nt), dim3(kThreadsPoly), 0, st, T, pc,
+                                       src, epi, ctl);
+                    return launch_check("k_exp_poly<51>");
                 }
-                auto kern = k_taylor<R, 102, kThreadsTaylor, kTaylorDeg, taylor_split(102), Src, Epi, Ctl>;
-                hipLaunchKernelGGL(kern, dim3(taylor_split(102) * nrhs * c->Nt), dim3(kThreadsTaylor), 0, st, T,
-                                   dk, emu, src, epi, ctl);
-                return launch_check("k_taylor<102>");
+                auto kern = k_exp_poly<R, 102, kThreadsPoly, kPolyDeg, poly_split(102), Src, Epi, Ctl>;
+                hipLaunchKernelGGL(kern, dim3(poly_split(102) * nrhs * c->Nt), dim3(kThreadsPoly), 0, st, T, pc,
+                                   src, epi, ctl);
+                return launch_check("k_exp_poly<102>");
             }
-            return fail(HUB_ERR_ARG, "internal: the Taylor kernel is FP32 only");
+            return fail(HUB_ERR_ARG, "internal: the polynomial stencil is FP32 only");
         }
         case OpKind::Whole51: {
             auto kern = k_fused_ct<R, 51, kThreads51, false, Src, Epi, Ctl>;
@@ -760,7 +765,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     const long long N = 2LL * prm->L * prm->L * prm->Nt;
     if ((long long)prm->nrhs_max * N >= (1LL << 40)) return fail(HUB_ERR_ARG, "problem too large");
     // every launch grid must fit a 32-bit block index: at most 2 * max(nrb, ncb) blocks per
-    // slice for the transforms (at least the Taylor stencil's 2 at L = 51 and 4 at L = 102), at
+    // slice for the transforms (at least the polynomial stencil's 2 at L = 51 and 4 at L = 102), at
     // most max(Nt, 1024) blocks per right-hand side for the linear stencil
     const SplitGeom g = split_geom(prm->L);
     const long long grid_per_rhs = lin ? std::max<long long>(prm->Nt, 1024)
@@ -798,8 +803,13 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     c->path = (prm->path == HUB_PATH_SPLIT || (prm->path == HUB_PATH_AUTO && !fits)) ? HUB_PATH_SPLIT
                                                                                       : HUB_PATH_FUSED;
     c->split_forced = prm->path == HUB_PATH_SPLIT;
-    c->taylor = !lin && prm->path == HUB_PATH_AUTO && (c->L == 51 || c->L == 102) &&
-                3.0 * std::fabs(c->delta * c->kappa) <= kTaylorMaxX;
+    {
+        const double x = 3.0 * std::fabs(c->delta * c->kappa);
+        if (!lin && prm->path == HUB_PATH_AUTO && (c->L == 51 || c->L == 102) && x <= kPolyMaxX) {
+            c->poly_err = exp_poly_ratios(x, kPolyDeg, &c->poly_a0, c->poly_ratio);
+            c->poly = c->poly_err >= 0.0 && c->poly_err <= kPolyTol;
+        }
+    }
 
     std::vector<double> roots, etab;
     if (!lin) build_tables(plan, c->delta * c->kappa, c->delta * prm->mu, roots, etab);

@@ -43,7 +43,10 @@ struct hub_ctx {
     int form = HUB_FORM_EXP;
     bool specialized = true;         // use a compile-time-L kernel when one exists
     bool split_forced = false;       // HUB_PATH_SPLIT requested: no fused kernel of any kind
-    bool taylor = false;             // FP32 operators by the Taylor-stencil kernel (HUB_PATH_AUTO, L = 51, 102)
+    bool poly = false;               // FP32 operators by the polynomial stencil (HUB_PATH_AUTO, L = 51, 102)
+    double poly_a0 = 1.0;            // its polynomial (exp_poly_ratios): a_0, a_k / a_{k-1}, error bound
+    double poly_ratio[9] = {};
+    double poly_err = -1.0;
     int lds_fused64 = 0, lds_fused32 = 0;
     int max_lds = 0;
     hub::FftPlan plan{};

@@ -1061,12 +1061,13 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
 }
 
-// ----------------------------------------------------------------------------- Taylor kernel
-// E = e^{delta mu} exp(delta kappa K) applied as its Taylor polynomial of degree DEG, evaluated by
-// Horner's rule y <- v + (delta kappa / j) K y, j = DEG..1: DEG nearest-neighbour stencil
-// sweeps over the slice instead of four L x L transforms.  The remainder after degree DEG is
-// at most x^{DEG+1}/(DEG+1)! e^x with x = 3 |delta kappa| (the largest eigenvalue of K is 3);
-// the host uses this kernel only where that is far below the precision's rounding.
+// ----------------------------------------------------------------------------- polynomial kernel
+// E = e^{delta mu} exp(delta kappa K) applied as e^{delta mu} p(delta kappa K) with p a polynomial of
+// degree DEG close to e^z on the spectrum [-x, x] of delta kappa K (x = 3 |delta kappa|; the
+// host's exp_poly_ratios gives p and its error bound, and uses this kernel only where that bound
+// is far below the precision's rounding).  p is evaluated in nested form,
+//     y <- v + c_j K y,  j = DEG..1,   result scale * y,   c_j = delta kappa a_j / a_{j-1},
+// so DEG nearest-neighbour stencil sweeps over the slice replace four L x L transforms.
 //
 // NSPLIT workgroups per slice split the columns n2: workgroup h writes columns
 // [h L / NSPLIT, (h + 1) L / NSPLIT) and carries H = ceil(DEG/2) halo columns on each side,
@@ -1080,7 +1081,7 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
 // L of them) are split into NT/32 strips of at most RMAX rows held in registers; the row above
 // and below a strip cross strips through LDS once per sweep.
 template <int L, int NT, int DEG, int NSPLIT>
-struct TayGeom {
+struct PolyGeom {
     static constexpr int H = (DEG + 1) / 2;
     static constexpr int W = (L + NSPLIT - 1) / NSPLIT + 2 * H;   // widest column range with its halos
     static constexpr int LPS = W <= 32 ? 32 : 64;        // lanes (columns) per strip
@@ -1105,11 +1106,20 @@ __device__ __forceinline__ cx<float> lane_next(cx<float> v) {
     return {lane_shift<kDppWaveShl1>(v.re), lane_shift<kDppWaveShl1>(v.im)};
 }
 
+// The polynomial's constants: c[j] = delta kappa a_j / a_{j-1} for sweep j = 1..8, and the final
+// scale e^{delta mu} a_0.
+template <typename R>
+struct PolyCoef {
+    R scale;
+    R c[9];
+};
+
 template <typename R, int L, int NT, int DEG, int NSPLIT, class Src, class Epi, class Ctl>
 __global__ void __launch_bounds__(NT)
-k_taylor(const OpTab<R> T, const R dk, const R emu, const Src src, const Epi epi, const Ctl ctl) {
+k_exp_poly(const OpTab<R> T, const PolyCoef<R> pc, const Src src, const Epi epi, const Ctl ctl) {
     static_assert(sizeof(R) == sizeof(float), "FP32 only: in FP64 the FFT kernels measured faster");
-    using G = TayGeom<L, NT, DEG, NSPLIT>;
+    static_assert(DEG >= 1 && DEG <= 8, "c[] holds eight sweeps");
+    using G = PolyGeom<L, NT, DEG, NSPLIT>;
     constexpr int LL = L * L, RM = G::RMAX, NS = G::NSTRIP;
     __shared__ cx<R> edgeA[2][NS][G::LPS];               // first row's A of each strip, per sweep parity
     __shared__ cx<R> edgeB[2][NS][G::LPS];               // last row's B
@@ -1186,7 +1196,7 @@ k_taylor(const OpTab<R> T, const R dk, const R emu, const Src src, const Epi epi
             __syncthreads();
             const cx<R> above = edgeB[par][sp][j];        // B of row r0 - 1 (the previous strip's last)
             const cx<R> below = edgeA[par][sn][j];        // A of row r0 + nr (the next strip's first)
-            const R ck = dk * (R)(1.0 / k);
+            const R ck = pc.c[k];
             // rows top to bottom, in place: row r's new A needs the old B of rows r and r - 1
             // (the latter carried in bup), its new B the old A of rows r and r + 1 (not yet
             // updated when row r is)
@@ -1209,8 +1219,8 @@ k_taylor(const OpTab<R> T, const R dk, const R emu, const Src src, const Epi epi
 #pragma unroll
             for (int r = 0; r < RM; ++r)
                 if (r < nr) {
-                    epi.store(rhs, t, (r0 + r) * L + n2, scale(emu, ya[r]), ea[r], T, sc, acc);
-                    epi.store(rhs, t, LL + (r0 + r) * L + n2, scale(emu, yb[r]), eb[r], T, sc, acc);
+                    epi.store(rhs, t, (r0 + r) * L + n2, scale(pc.scale, ya[r]), ea[r], T, sc, acc);
+                    epi.store(rhs, t, LL + (r0 + r) * L + n2, scale(pc.scale, yb[r]), eb[r], T, sc, acc);
                 }
         }
     }

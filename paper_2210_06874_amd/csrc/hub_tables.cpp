@@ -9,6 +9,7 @@
 // A chemical potential mu multiplies every time hop by e^{delta mu} (Sec. 1 Hamiltonian:
 // mu couples to the charge; Sec. 3 weight det(M[phi,mu] M[phi,-mu]^dag)).
 #include <cmath>
+#include <utility>
 
 #include "hub_tables.hpp"
 
@@ -89,6 +90,65 @@ void build_tables(const FftPlan& plan, double dk, double dmu, std::vector<double
             e[3] = 0.0;
         }
     }
+}
+
+double exp_poly_ratios(double x, int deg, double* a0, double* ratio) {
+    if (deg < 1 || deg > 8 || !(x >= 0.0) || !std::isfinite(x)) return -1.0;
+    const int n = deg + 1;
+    double a[9] = {};
+    if (x < 1e-3) {
+        a[0] = 1.0;
+        for (int k = 1; k < n; ++k) a[k] = a[k - 1] / k;
+    } else {
+        // interpolate in t = z / x on the Chebyshev nodes of [-1, 1]: b_k of p = sum b_k t^k
+        // from the n x n Vandermonde system (Gaussian elimination, partial pivoting), then
+        // a_k = b_k / x^k
+        const double pi = 3.14159265358979323846;
+        double V[9][10];
+        for (int i = 0; i < n; ++i) {
+            const double t = std::cos((2.0 * i + 1.0) * pi / (2.0 * n));
+            double tp = 1.0;
+            for (int k = 0; k < n; ++k) {
+                V[i][k] = tp;
+                tp *= t;
+            }
+            V[i][n] = std::exp(x * t);
+        }
+        for (int col = 0; col < n; ++col) {
+            int piv = col;
+            for (int i = col + 1; i < n; ++i)
+                if (std::fabs(V[i][col]) > std::fabs(V[piv][col])) piv = i;
+            for (int k = 0; k <= n; ++k) std::swap(V[col][k], V[piv][k]);
+            for (int i = col + 1; i < n; ++i) {
+                const double f = V[i][col] / V[col][col];
+                for (int k = col; k <= n; ++k) V[i][k] -= f * V[col][k];
+            }
+        }
+        double b[9];
+        for (int i = n - 1; i >= 0; --i) {
+            double s = V[i][n];
+            for (int k = i + 1; k < n; ++k) s -= V[i][k] * b[k];
+            b[i] = s / V[i][i];
+        }
+        double xp = 1.0;
+        for (int k = 0; k < n; ++k) {
+            a[k] = b[k] / xp;
+            xp *= x;
+        }
+    }
+    for (int k = 0; k < n; ++k)
+        if (!(a[k] > 0.0)) return -1.0;
+    *a0 = a[0];
+    ratio[0] = 0.0;
+    for (int k = 1; k < n; ++k) ratio[k] = a[k] / a[k - 1];
+    double err = 0.0;
+    for (int i = 0; i <= 4000; ++i) {
+        const double z = x * (-1.0 + i / 2000.0);
+        double p = a[deg];
+        for (int k = deg - 1; k >= 0; --k) p = a[k] + z * p;
+        err = std::fmax(err, std::fabs(p - std::exp(z)));
+    }
+    return err;
 }
 
 }  // namespace hub

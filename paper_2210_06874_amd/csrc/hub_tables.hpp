@@ -31,4 +31,16 @@ int digit_reversed_position(const FftPlan& plan, int k);
 void build_tables(const FftPlan& plan, double delta_kappa, double delta_mu, std::vector<double>& roots,
                   std::vector<double>& etab);
 
+// A polynomial p(z) = sum_{k<=deg} a_k z^k close to e^z on z in [-x, x], for applying
+// exp(delta kappa K) as p(delta kappa K): the spectrum of delta kappa K lies in [-x, x] with
+// x = 3 |delta kappa| (K's eigenvalues are +-|f(k)|, |f| <= 3), so the operator error in the
+// 2-norm is at most max |p(z) - e^z| over [-x, x].  p is the Chebyshev interpolant of e^z on
+// [-x, x] (nodes x cos((2i+1) pi / (2 deg + 2))); for x < 1e-3 the Taylor polynomial, which is
+// then as accurate.  Returned in the nested form the stencil evaluates,
+//     p(z) v = a_0 (v + r_1 z (v + r_2 z (v + ... + r_deg z v))),   r_k = a_k / a_{k-1},
+// with a0 = a_0 and ratio[k] = r_k (k = 1..deg, ratio[0] unused).  Returns the largest
+// |p(z) - e^z| over 4001 evenly spaced points of [-x, x], or a negative value when deg is
+// outside 1..8 or some a_k is not positive (the nested form needs every a_k > 0).
+double exp_poly_ratios(double x, int deg, double* a0, double* ratio);
+
 }  // namespace hub

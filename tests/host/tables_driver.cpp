@@ -1,12 +1,23 @@
-// Prints the host-side plan and tables of the library for one L and delta*kappa, so the
-// CPU tests can check them against independent references.  Built by the tests with g++.
+// Prints the host-side plan and tables of the library for one L and delta*kappa (or, with
+// "poly X DEG", the exponential's polynomial on [-X, X]), so the CPU tests can check them
+// against independent references.  Built by the tests with g++.
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "hub_tables.hpp"
 
 int main(int argc, char** argv) {
+    if (argc == 4 && std::string(argv[1]) == "poly") {      // poly X DEG: the stencil's polynomial
+        double a0 = 0.0, r[9] = {};
+        const int deg = std::atoi(argv[3]);
+        const double err = hub::exp_poly_ratios(std::atof(argv[2]), deg, &a0, r);
+        std::printf("err %.17g\na0 %.17g\nratios", err, a0);
+        for (int k = 1; k <= deg; ++k) std::printf(" %.17g", r[k]);
+        std::printf("\n");
+        return 0;
+    }
     if (argc != 3 && argc != 4) return 2;
     const int L = std::atoi(argv[1]);
     const double dk = std::atof(argv[2]);

@@ -1,5 +1,6 @@
 """CPU checks of the C ABI and of the host-side logic (no device calls)."""
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -144,6 +145,40 @@ def test_momentum_hopping_table_is_the_2x2_exponential(tmp_path, L, dk, dmu):
             tol = 5e-15 * max(1.0, np.abs(E).max())      # a few ulp of the largest entry
             np.testing.assert_allclose([c, sr + 1j * si], [E[0, 0].real, E[0, 1]], rtol=0, atol=tol)
             np.testing.assert_allclose(E[1, 0], sr - 1j * si, rtol=0, atol=tol)
+
+
+def _poly(tmp_path, x, deg):
+    _tables(tmp_path, 3, 0.1)                         # builds the driver
+    out = subprocess.run([str(tmp_path / "tables"), "poly", repr(x), str(deg)], capture_output=True, text=True,
+                         check=True).stdout.splitlines()
+    err = float(out[0].split()[1])
+    a0 = float(out[1].split()[1])
+    ratios = [float(v) for v in out[2].split()[1:]]
+    return err, np.concatenate([[a0], a0 * np.cumprod(ratios)])
+
+
+@pytest.mark.parametrize("x", [0.0, 5e-4, 0.05, 0.1875, 0.25, 0.5])
+def test_exp_polynomial_of_the_stencil(tmp_path, x):
+    """The degree-5 polynomial p with which the FP32 stencil applies exp(dk K), on the spectrum
+    [-x, x] of dk K (x = 3|dk|): rebuilt from a_0 and the ratios the kernel uses, it is numpy's
+    Chebyshev interpolant of e^z on [-x, x] (first-kind nodes; the Taylor polynomial below
+    x = 1e-3), its reported error is max |p(z) - e^z| on a dense grid, and that error obeys the
+    interpolation bound 2 (x/2)^6 e^x / 6!: 1.1e-8 at the largest admitted step x = 0.25, 1.9e-9
+    at the paper's x = 0.1875."""
+    err, a = _poly(tmp_path, x, 5)
+    if x < 1e-3:
+        ref = 1.0 / np.array([math.factorial(k) for k in range(6)])
+    else:
+        b = np.polynomial.chebyshev.cheb2poly(np.polynomial.chebyshev.chebinterpolate(lambda t: np.exp(x * t), 5))
+        ref = b / x ** np.arange(6)
+    z = np.linspace(-x, x, 20001)
+    p = np.polynomial.polynomial.polyval(z, a)
+    np.testing.assert_allclose(p, np.polynomial.polynomial.polyval(z, ref), rtol=0, atol=1e-14)
+    dense = np.abs(p - np.exp(z)).max()
+    assert dense <= max(1.02 * err, 1e-15) and err <= dense + 1e-16, (err, dense)
+    assert dense <= 2 * (x / 2) ** 6 * math.exp(x) / math.factorial(6) + 1e-15
+    if x <= 0.25:
+        assert err <= 1.2e-8
 
 
 def test_unsupported_lengths_have_no_plan(tmp_path):

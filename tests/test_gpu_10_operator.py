@@ -72,7 +72,7 @@ def test_apply_diff_workload_fp64():
 @pytest.mark.parametrize("prec,path", [("fp64", "auto"), ("fp32", "auto"), ("fp32", "fused")])
 def test_apply_precision_workload(prec, path):
     """L = 51, Nt = 128: the full operator against the oracle's Krylov-exp route (FP32: the
-    default Taylor-stencil kernel and the transform kernels of the forced fused path)."""
+    default polynomial-stencil kernel and the transform kernels of the forced fused path)."""
     w = PREC
     print(f"[case] apply {prec} {w.name} path={path}", flush=True)
     phi, v = draw_inputs(w, seed=14)
@@ -97,7 +97,7 @@ def test_apply_precision_workload(prec, path):
 @pytest.mark.parametrize("nrhs", [1, 2])
 def test_apply_fp32_both_operators_precision_workload(nrhs, path):
     """L = 51, N_t = 128 in FP32: M and M^dag, every entry, with one and two right-hand sides,
-    against the oracle applied to the same FP32-rounded inputs.  path auto: the Taylor-stencil
+    against the oracle applied to the same FP32-rounded inputs.  path auto: the polynomial-stencil
     kernel (two workgroups per slice, each writing half the columns); fused: the transform
     kernels (one right-hand side, 128 slices: two workgroups per slice, each writing one
     sublattice; two, 256 slices: one workgroup per slice)."""
@@ -159,7 +159,7 @@ def _stress_slices(op, phi, v, slices, dagger):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_apply_stress_workload_sampled(prec, kernel):
     """L = 102, Nt = 192, 4 right-hand sides in one call: sampled slices, including both wrap
-    slices, against the oracle (FP64: split path; FP32: the default Taylor stencil and the
+    slices, against the oracle (FP64: split path; FP32: the default polynomial stencil and the
     sublattice kernel)."""
     if prec == "fp64" and kernel == "sublattice":
         pytest.skip("the sublattice kernel is FP32 only")
@@ -259,24 +259,24 @@ def test_apply_with_chemical_potential(mu):
 
 @pytest.mark.parametrize("dag", [False, True])
 def test_sublattice_and_split_kernels_agree(dag):
-    """L = 102 in FP32: the default Taylor-stencil kernel, the one-workgroup-per-slice kernel that
+    """L = 102 in FP32: the default polynomial-stencil kernel, the one-workgroup-per-slice kernel that
     keeps one sublattice's spectrum in registers (selected by the sublattice launch mode) and the
     three-kernel split path agree (all against the oracle on sampled slices in
     test_apply_stress_workload_sampled)."""
     w = STRESS
-    print(f"[case] Taylor vs sublattice vs split dag={dag}", flush=True)
+    print(f"[case] polynomial vs sublattice vs split dag={dag}", flush=True)
     phi, v = draw_inputs(w, seed=18, nrhs=2)
     P32, V32 = to_dev(phi.astype(np.float32)), to_dev(v.astype(np.complex64))
     a = _hub(w, "auto", nrhs=2)
     b = _hub(w, "split", nrhs=2)
     fa = a.apply_Mdag_c64 if dag else a.apply_M_c64
     fb = b.apply_Mdag_c64 if dag else b.apply_M_c64
-    taylor = to_np(fa(P32, V32))
+    poly = to_np(fa(P32, V32))
     a.set_cg_launch(sublattice=True)
     sub = to_np(fa(P32, V32))
     a.set_cg_launch()
     split = to_np(fb(P32, V32))
-    assert_close_elementwise(taylor, split, 4e-6, "Taylor vs split")
+    assert_close_elementwise(poly, split, 4e-6, "polynomial vs split")
     assert_close_elementwise(sub, split, 4e-6, "sub vs split")
 
 
@@ -468,7 +468,7 @@ def test_production_lengths_at_odd_shapes(L, Nt, nrhs, path):
     """The compile-time L = 51 and L = 102 kernels on both sides of the two-workgroup switch
     (fewer than 256 slices), with several right-hand sides, a single slice and odd N_t: M, M^dag,
     FP32 M and M^dag and the force on sampled slices against the oracle's Krylov route (at
-    L = 51 FP32 both the Taylor-stencil kernel of the default path and the transform kernels)."""
+    L = 51 FP32 both the polynomial-stencil kernel of the default path and the transform kernels)."""
     from paper_2210_06874_amd import Hubbard
     print(f"[case] production length L={L} Nt={Nt} nrhs={nrhs} path={path}", flush=True)
     w = Lattice(f"L{L}_Nt{Nt}", L, Nt, 0.0625 * Nt, 3.9, nrhs=nrhs)
@@ -499,18 +499,19 @@ def test_production_lengths_at_odd_shapes(L, Nt, nrhs, path):
 
 @pytest.mark.parametrize("beta,Nt,kappa,mu", [(8.0, 128, 1.0, 0.0), (8.0, 128, -1.0, 0.3), (8.0, 96, 1.0, -0.4),
                                              (8.0, 32, 1.0, 0.0), (2.0, 4, -1.0, 0.2)])
-def test_taylor_stencil_and_transform_kernels_at_L51(beta, Nt, kappa, mu):
-    """FP32 at L = 51: the default path applies E by its degree-6 Taylor polynomial while
-    x = 3|delta kappa| <= 0.25 (here x = 0.1875 with either sign of kappa, 0.25 exactly at
-    Nt = 96, where the remainder bound is largest) and by the transforms above it (x = 0.75,
-    1.5), and the forced fused path always by the transforms.  Every entry of M and M^dag of
-    both, with mu != 0 (e^{delta mu} scales E), within 1e-6 of the largest entry of the
-    oracle's result on the same FP32-rounded inputs: FP32 rounding (random shapes show at most
-    3e-7), so the polynomial's truncation (at most 1.3e-8) is invisible and a wrong choice of
-    kernel (x = 0.75 by degree 6: about 6e-5) is not."""
+def test_polynomial_stencil_and_transform_kernels_at_L51(beta, Nt, kappa, mu):
+    """FP32 at L = 51: the default path applies E by a degree-5 polynomial of dk K (the
+    Chebyshev interpolant of e^z on the spectrum [-x, x], x = 3|dk|) while x <= 0.25 (here
+    x = 0.1875 with either sign of kappa, 0.25 exactly at Nt = 96, where the polynomial's error
+    bound is largest) and by the transforms above it (x = 0.75, 1.5), and the forced fused path
+    always by the transforms.  Every entry of M and M^dag of both, with mu != 0 (e^{delta mu}
+    scales E), within 1e-6 of the largest entry of the oracle's result on the same FP32-rounded
+    inputs: FP32 rounding (random shapes show at most 3e-7), so the polynomial's error (at most
+    1.1e-8) is invisible and a wrong choice of kernel (x = 0.75 by the polynomial: about 2e-5)
+    is not."""
     from paper_2210_06874_amd import Hubbard
     L = 51
-    print(f"[case] Taylor vs transform L={L} Nt={Nt} beta={beta} kappa={kappa} mu={mu}", flush=True)
+    print(f"[case] polynomial vs transform L={L} Nt={Nt} beta={beta} kappa={kappa} mu={mu}", flush=True)
     w = Lattice(f"L{L}_Nt{Nt}", L, Nt, beta, 3.85, kappa=kappa)
     phi, v = draw_inputs(w, seed=Nt + 5, nrhs=1)
     p32, v32 = phi.astype(np.float32), v.astype(np.complex64)

@@ -195,7 +195,7 @@ def _free_cond(w):
 def test_cg_free_plane_wave_at_scale(w, prec, path):
     """phi = 0, chi a plane wave: x = chi / |1 - e^{-i omega} e^{delta eps}|^2 exactly (P2 through
     the solver); the returned x is within cond * tol of it.  At L = 51 the mixed solve iterates
-    with the Taylor-stencil kernels by default and with the transform kernels when forced."""
+    with the polynomial-stencil kernels by default and with the transform kernels when forced."""
     if path == "fused" and w.L != 51:
         pytest.skip("the forced fused path needs an FP64 slice that fits LDS (L = 51 only here)")
     print(f"[case] cg plane wave {prec} {w.name} path={path}", flush=True)
