@@ -233,10 +233,13 @@ def linear_leg(w, dev, P32, V32, out32, steps: int, warmup: int) -> dict:
     return out
 
 
-def stress_leg(dev, steps: int) -> dict:
+def stress_leg(dev, steps: int, persistent: bool = True) -> dict:
     """The four-right-hand-side L = 102, Nt = 192 workload (beta = 12, U = 3.9): one launch
     applies M to all four vectors (FP32 and FP64), and a mixed-precision CG on the weak-field
-    input runs `steps` blocks of 50 iterations, all four right-hand sides in every launch."""
+    input runs `steps` blocks of 50 iterations, all four right-hand sides in every launch: with
+    the default kernels (the polynomial stencil), with the sublattice kernel, and (unless
+    persistent is False: profilers that cannot follow a cooperative launch) as one persistent
+    launch per block of iterations."""
     import torch
     from paper_2210_06874_amd import Hubbard
     from workloads import STRESS, draw_inputs, draw_weak_field
@@ -254,8 +257,8 @@ def stress_leg(dev, steps: int) -> dict:
     Pw, Cw = torch.from_numpy(pw).to(dev), torch.from_numpy(cw).to(dev)
     n_it = 50 * max(1, steps)
     cg = {}
-    for mode in ("persistent", "two_kernel"):
-        hub.set_cg_launch(persistent=(mode == "persistent"))
+    for mode in (("persistent",) if persistent else ()) + ("sublattice", "two_kernel"):
+        hub.set_cg_launch(persistent=(mode == "persistent"), sublattice=(mode == "sublattice"))
         hub.cg_solve(Pw, Cw, tol=1e-10, prec="mixed", max_iter=50, raise_on_error=False)   # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -275,8 +278,9 @@ def stress_leg(dev, steps: int) -> dict:
             "cg_iterations": cg["two_kernel"]["iterations"], "cg_GBs": cg["two_kernel"]["GBs"],
             "cg_mixed_by_launch": cg,
             "timing": "operators: HIP graphs, events on their stream; CG: wall time of one solve of "
-                      f"{n_it} iterations (includes its reliable updates), persistent launch and two "
-                      "launches per iteration"}
+                      f"{n_it} iterations (includes its reliable updates); two launches per iteration "
+                      "with the default kernels (cg_mixed_us_per_iteration) or the sublattice kernel, "
+                      "and one persistent launch per block of iterations"}
 
 
 def weak_field_leg(w, dev, hub, steps: int) -> dict:
@@ -337,6 +341,8 @@ def main() -> int:
     ap.add_argument("--copy-floor", action="store_true",
                     help="only time plain device-to-device copies (HIP graphs) moving the bytes of one "
                          "FP32 / FP64 operator application and larger sizes, one JSON line")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="with --stress: leave out the persistent (cooperative) CG launch")
     ap.add_argument("--stress", action="store_true",
                     help="instead of the force step: the four-right-hand-side L = 102, Nt = 192 "
                          "workload (operator launches and mixed CG iterations), one JSON line")
@@ -374,7 +380,7 @@ def main() -> int:
         print("probe done")
         return 0
     if args.stress:
-        print(json.dumps(stress_leg(dev, args.steps)))
+        print(json.dumps(stress_leg(dev, args.steps, persistent=not args.no_persistent)))
         return 0
     if args.copy_floor:
         print(json.dumps(copy_floor(w, dev)))

@@ -520,9 +520,11 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
                    const hub_cg_opts& o, hub_cg_info* info, hipStream_t st) {
     const bool lin = c->form == HUB_FORM_LINEAR;
     // Phases: e^{i phi} tabulated once per solve in FP64, and in FP32 for FP32 iterations of
-    // the exponential form (transform-bound kernels).  FP32 iterations of the linear form
-    // (bandwidth-bound stencils) read an FP32 copy of the angles instead, half the bytes of
-    // a table, and evaluate the phase per use on the hardware sin/cos units.
+    // the exponential form on the transform kernels.  FP32 iterations of the bandwidth-bound
+    // stencils (the linear form, the polynomial stencil of the exponential form) read an FP32
+    // copy of the angles instead, half the bytes of a table, and evaluate the phase per use on
+    // the hardware sin/cos units.
+    const bool angles = lin || (sizeof(Rlo) == sizeof(float) && op_kind<Rlo>(c, nrhs) == OpKind::Poly);
     cx<double>* ph64 = static_cast<cx<double>*>(c->ph64);
     const cx<Rlo>* ph_lo = reinterpret_cast<const cx<Rlo>*>(ph64);
     const Rlo* phi_lo = reinterpret_cast<const Rlo*>(phi);
@@ -530,7 +532,7 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     hub_status s0 = launch_check("k_phase_table<double>");
     if (s0 != HUB_OK) return s0;
     if constexpr (sizeof(Rlo) == sizeof(float)) {
-        if (!lin) {
+        if (!angles) {
             hipLaunchKernelGGL(k_phase_table<float>, dim3(1024), dim3(kThreads), 0, st, phi,
                                static_cast<cx<float>*>(c->ph32), c->N);
             s0 = launch_check("k_phase_table<float>");
@@ -629,6 +631,12 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
                     if (q != HUB_OK) return q;
                     q = run_lin<Rlo, false>(c, nrhs, tab_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
                 }
+            } else if (angles) {
+                q = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p},
+                                EpiSearchMdag<Rlo, PhAngle<Rlo>>{rlo, p, tv, ang_lo}, k1, st);
+                if (q != HUB_OK) return q;
+                q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhAngle<Rlo>>{tv, ang_lo},
+                                EpiUpdate<Rlo>{tv, p, xlo, rlo}, k2, st);
             } else {
                 q = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p},
                                 EpiSearchMdag<Rlo, PhTable<Rlo>>{rlo, p, tv, tab_lo}, k1, st);
