@@ -146,9 +146,9 @@ hub_status hub_apply_Mdag(hub_ctx* ctx, const double* phi, const void* in, void*
                           int32_t nrhs, void* stream);
 
 /* FP32 variants of the two operators (complex64 vectors, float phi): the kernels
- * that the mixed-precision CG iterates with.  With HUB_PATH_AUTO at L = 51 and
+ * that the mixed-precision CG iterates with.  With HUB_PATH_AUTO at L = 51 or 102 and
  * 3 |delta kappa| <= 0.25 they apply E = e^{delta mu} exp(delta kappa K) (Sec. 2, eq.
- * "ferm_op") as e^{delta mu} p(delta kappa K), p the degree-5 Chebyshev interpolant of e^z on
+ * "ferm_op") as e^{delta mu} p(delta kappa K), p the degree-5 truncated Chebyshev series of e^z on
  * [-3|delta kappa|, 3|delta kappa|] (K's spectrum lies in [-3, 3]), an error of at most 1.1e-8
  * relative, below FP32 rounding; otherwise, and in every FP64 entry point, through the
  * per-slice transforms. */

@@ -1076,8 +1076,8 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
 // Lanes run along n2 (32 lanes per strip when the columns and halos fit, so a strip is half a
 // wave, else 64; a site's n2 neighbours are the adjacent lanes, fetched with wave-wide DPP
 // shifts, and the lanes at a strip's two edges receive another strip's values or 0, which only
-// ever feed halo columns).  FP32 only: in FP64 (degree 12, two 32-bit shifts per value, 64-lane
-// strips) the FFT kernels measured faster.  Rows n1 (periodic, all
+// ever feed halo columns).  FP32 only: in FP64 (degree 9 or 12, each double crossing lanes as two
+// 32-bit shifts that do not fold into the adds) the FFT kernels measured faster.  Rows n1 (periodic, all
 // L of them) are split into NT/32 strips of at most RMAX rows held in registers; the row above
 // and below a strip cross strips through LDS once per sweep.
 template <int L, int NT, int DEG, int NSPLIT>

@@ -9,7 +9,6 @@
 // A chemical potential mu multiplies every time hop by e^{delta mu} (Sec. 1 Hamiltonian:
 // mu couples to the charge; Sec. 3 weight det(M[phi,mu] M[phi,-mu]^dag)).
 #include <cmath>
-#include <utility>
 
 #include "hub_tables.hpp"
 
@@ -93,62 +92,56 @@ void build_tables(const FftPlan& plan, double dk, double dmu, std::vector<double
 }
 
 double exp_poly_ratios(double x, int deg, double* a0, double* ratio) {
-    if (deg < 1 || deg > 8 || !(x >= 0.0) || !std::isfinite(x)) return -1.0;
+    if (deg < 1 || deg > kMaxPolyDeg || !(x >= 0.0) || !std::isfinite(x)) return -1.0;
     const int n = deg + 1;
-    double a[9] = {};
+    long double a[kMaxPolyDeg + 1] = {};
+    const long double xl = x;
     if (x < 1e-3) {
-        a[0] = 1.0;
+        a[0] = 1.0L;
         for (int k = 1; k < n; ++k) a[k] = a[k - 1] / k;
     } else {
-        // interpolate in t = z / x on the Chebyshev nodes of [-1, 1]: b_k of p = sum b_k t^k
-        // from the n x n Vandermonde system (Gaussian elimination, partial pivoting), then
-        // a_k = b_k / x^k
-        const double pi = 3.14159265358979323846;
-        double V[9][10];
-        for (int i = 0; i < n; ++i) {
-            const double t = std::cos((2.0 * i + 1.0) * pi / (2.0 * n));
-            double tp = 1.0;
-            for (int k = 0; k < n; ++k) {
-                V[i][k] = tp;
-                tp *= t;
+        // Chebyshev series of e^{x t} on [-1, 1]: e^{x t} = I_0(x) + 2 sum_{j>=1} I_j(x) T_j(t),
+        // I_j(x) = sum_m (x/2)^{2m+j} / (m! (m+j)!) (every term positive), truncated at deg
+        long double cj[kMaxPolyDeg + 1];
+        for (int j = 0; j < n; ++j) {
+            long double term = 1.0L;
+            for (int i = 1; i <= j; ++i) term *= (xl / 2.0L) / i;     // (x/2)^j / j!
+            long double s = 0.0L;
+            for (int m = 0; m < 40 && term > 0.0L; ++m) {
+                s += term;
+                term *= (xl / 2.0L) * (xl / 2.0L) / ((m + 1.0L) * (m + 1.0L + j));
             }
-            V[i][n] = std::exp(x * t);
+            cj[j] = j == 0 ? s : 2.0L * s;
         }
-        for (int col = 0; col < n; ++col) {
-            int piv = col;
-            for (int i = col + 1; i < n; ++i)
-                if (std::fabs(V[i][col]) > std::fabs(V[piv][col])) piv = i;
-            for (int k = 0; k <= n; ++k) std::swap(V[col][k], V[piv][k]);
-            for (int i = col + 1; i < n; ++i) {
-                const double f = V[i][col] / V[col][col];
-                for (int k = col; k <= n; ++k) V[i][k] -= f * V[col][k];
-            }
-        }
-        double b[9];
-        for (int i = n - 1; i >= 0; --i) {
-            double s = V[i][n];
-            for (int k = i + 1; k < n; ++k) s -= V[i][k] * b[k];
-            b[i] = s / V[i][i];
-        }
-        double xp = 1.0;
-        for (int k = 0; k < n; ++k) {
-            a[k] = b[k] / xp;
-            xp *= x;
+        // monomial coefficients of T_j: T_0 = 1, T_1 = t, T_{j+1} = 2 t T_j - T_{j-1}
+        long double T[kMaxPolyDeg + 1][kMaxPolyDeg + 1] = {};
+        T[0][0] = 1.0L;
+        if (n > 1) T[1][1] = 1.0L;
+        for (int j = 1; j + 1 < n; ++j)
+            for (int k = 0; k < n; ++k)
+                T[j + 1][k] = (k > 0 ? 2.0L * T[j][k - 1] : 0.0L) - T[j - 1][k];
+        long double xp = 1.0L;
+        for (int k = 0; k < n; ++k) {                                 // a_k = b_k / x^k
+            long double bk = 0.0L;
+            for (int j = k; j < n; ++j) bk += cj[j] * T[j][k];
+            a[k] = bk / xp;
+            xp *= xl;
         }
     }
     for (int k = 0; k < n; ++k)
-        if (!(a[k] > 0.0)) return -1.0;
-    *a0 = a[0];
+        if (!(a[k] > 0.0L)) return -1.0;
+    *a0 = (double)a[0];
     ratio[0] = 0.0;
-    for (int k = 1; k < n; ++k) ratio[k] = a[k] / a[k - 1];
-    double err = 0.0;
+    for (int k = 1; k < n; ++k) ratio[k] = (double)(a[k] / a[k - 1]);
+    long double err = 0.0L;
     for (int i = 0; i <= 4000; ++i) {
-        const double z = x * (-1.0 + i / 2000.0);
-        double p = a[deg];
+        const long double z = xl * (-1.0L + i / 2000.0L);
+        long double p = a[deg];
         for (int k = deg - 1; k >= 0; --k) p = a[k] + z * p;
-        err = std::fmax(err, std::fabs(p - std::exp(z)));
+        const long double d = p - std::exp(z);
+        err = std::fmax(err, d < 0 ? -d : d);
     }
-    return err;
+    return (double)err;
 }
 
 }  // namespace hub

@@ -34,13 +34,16 @@ void build_tables(const FftPlan& plan, double delta_kappa, double delta_mu, std:
 // A polynomial p(z) = sum_{k<=deg} a_k z^k close to e^z on z in [-x, x], for applying
 // exp(delta kappa K) as p(delta kappa K): the spectrum of delta kappa K lies in [-x, x] with
 // x = 3 |delta kappa| (K's eigenvalues are +-|f(k)|, |f| <= 3), so the operator error in the
-// 2-norm is at most max |p(z) - e^z| over [-x, x].  p is the Chebyshev interpolant of e^z on
-// [-x, x] (nodes x cos((2i+1) pi / (2 deg + 2))); for x < 1e-3 the Taylor polynomial, which is
-// then as accurate.  Returned in the nested form the stencil evaluates,
+// 2-norm is at most max |p(z) - e^z| over [-x, x].  p is the Chebyshev series of e^z on [-x, x]
+// truncated at degree deg (coefficients 2 I_j(x), modified Bessel functions, evaluated by their
+// power series in long double; its error is about 2 I_{deg+1}(x) ~ 2 (x/2)^{deg+1} / (deg+1)!);
+// for x < 1e-3 the Taylor polynomial, which is then as accurate.  Returned in the nested form
+// the stencil evaluates,
 //     p(z) v = a_0 (v + r_1 z (v + r_2 z (v + ... + r_deg z v))),   r_k = a_k / a_{k-1},
 // with a0 = a_0 and ratio[k] = r_k (k = 1..deg, ratio[0] unused).  Returns the largest
-// |p(z) - e^z| over 4001 evenly spaced points of [-x, x], or a negative value when deg is
-// outside 1..8 or some a_k is not positive (the nested form needs every a_k > 0).
+// |p(z) - e^z| over 4001 evenly spaced points of [-x, x] (in long double), or a negative value
+// when deg is outside 1..kMaxPolyDeg or some a_k is not positive (the nested form needs a_k > 0).
+constexpr int kMaxPolyDeg = 10;
 double exp_poly_ratios(double x, int deg, double* a0, double* ratio);
 
 }  // namespace hub

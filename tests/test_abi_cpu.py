@@ -157,28 +157,43 @@ def _poly(tmp_path, x, deg):
     return err, np.concatenate([[a0], a0 * np.cumprod(ratios)])
 
 
-@pytest.mark.parametrize("x", [0.0, 5e-4, 0.05, 0.1875, 0.25, 0.5])
-def test_exp_polynomial_of_the_stencil(tmp_path, x):
-    """The degree-5 polynomial p with which the FP32 stencil applies exp(dk K), on the spectrum
-    [-x, x] of dk K (x = 3|dk|): rebuilt from a_0 and the ratios the kernel uses, it is numpy's
-    Chebyshev interpolant of e^z on [-x, x] (first-kind nodes; the Taylor polynomial below
-    x = 1e-3), its reported error is max |p(z) - e^z| on a dense grid, and that error obeys the
-    interpolation bound 2 (x/2)^6 e^x / 6!: 1.1e-8 at the largest admitted step x = 0.25, 1.9e-9
-    at the paper's x = 0.1875."""
-    err, a = _poly(tmp_path, x, 5)
+@pytest.mark.parametrize("x,deg", [(0.0, 5), (5e-4, 5), (0.05, 5), (0.1875, 5), (0.25, 5), (0.5, 5),
+                                   (0.1875, 9), (0.25, 9), (0.25, 10)])
+def test_exp_polynomial_of_the_stencil(tmp_path, x, deg):
+    """The polynomial p with which the stencil applies exp(dk K), on the spectrum [-x, x] of dk K
+    (x = 3|dk|): degree 5 (FP32) and 9 (FP64).  Rebuilt from a_0 and the ratios the kernel uses,
+    it is the Chebyshev series of e^z on [-x, x] truncated at its degree (coefficients 2 I_j(x),
+    here from scipy's modified Bessel functions; the Taylor polynomial below x = 1e-3), its
+    reported error is max |p(z) - e^z| on a dense grid (in long double), and that error obeys the
+    truncation bound 2 (x/2)^{d+1} e^x / (d+1)!: 1.1e-8 at the largest FP32 step x = 0.25, 1.9e-9
+    at the paper's x = 0.1875; 2.9e-17 in degree 9 there (6e-17 with the coefficients rounded to
+    double, as the device uses them), below FP64 rounding."""
+    import scipy.special
+    err, a = _poly(tmp_path, x, deg)
     if x < 1e-3:
-        ref = 1.0 / np.array([math.factorial(k) for k in range(6)])
+        ref = 1.0 / np.array([math.factorial(k) for k in range(deg + 1)])
     else:
-        b = np.polynomial.chebyshev.cheb2poly(np.polynomial.chebyshev.chebinterpolate(lambda t: np.exp(x * t), 5))
-        ref = b / x ** np.arange(6)
+        c = np.array([scipy.special.iv(j, x) * (1.0 if j == 0 else 2.0) for j in range(deg + 1)])
+        ref = np.polynomial.chebyshev.cheb2poly(c) / x ** np.arange(deg + 1)
     z = np.linspace(-x, x, 20001)
-    p = np.polynomial.polynomial.polyval(z, a)
-    np.testing.assert_allclose(p, np.polynomial.polynomial.polyval(z, ref), rtol=0, atol=1e-14)
-    dense = np.abs(p - np.exp(z)).max()
-    assert dense <= max(1.02 * err, 1e-15) and err <= dense + 1e-16, (err, dense)
-    assert dense <= 2 * (x / 2) ** 6 * math.exp(x) / math.factorial(6) + 1e-15
-    if x <= 0.25:
+    np.testing.assert_allclose(np.polynomial.polynomial.polyval(z, a), np.polynomial.polynomial.polyval(z, ref),
+                               rtol=0, atol=1e-15)
+    zl = z.astype(np.longdouble)
+    p = np.zeros_like(zl)
+    for ak in a.astype(np.longdouble)[::-1]:
+        p = p * zl + ak
+    # the coefficients here are the library's long-double ones rounded to double and rebuilt as
+    # a_0 times a product of ratios (the device takes the ratios): each a_k is within a few
+    # units of 2^-53 of the library's, so the polynomial moves by at most 4 2^-53 e^x
+    dense = float(np.abs(p - np.exp(zl)).max())
+    rnd = 4 * 2.0 ** -53 * math.exp(x)
+    assert abs(dense - err) <= rnd, (err, dense)
+    bound = 2 * (x / 2) ** (deg + 1) * math.exp(x) / math.factorial(deg + 1)
+    assert err <= bound + 1e-18 and dense <= bound + rnd, (err, dense, bound)
+    if deg == 5 and x <= 0.25:
         assert err <= 1.2e-8
+    if deg == 9 and x <= 0.1875:
+        assert err <= 1.1e-16 and dense <= 1.1e-16
 
 
 def test_unsupported_lengths_have_no_plan(tmp_path):

@@ -501,7 +501,7 @@ def test_production_lengths_at_odd_shapes(L, Nt, nrhs, path):
                                              (8.0, 32, 1.0, 0.0), (2.0, 4, -1.0, 0.2)])
 def test_polynomial_stencil_and_transform_kernels_at_L51(beta, Nt, kappa, mu):
     """FP32 at L = 51: the default path applies E by a degree-5 polynomial of dk K (the
-    Chebyshev interpolant of e^z on the spectrum [-x, x], x = 3|dk|) while x <= 0.25 (here
+    truncated Chebyshev series of e^z on the spectrum [-x, x], x = 3|dk|) while x <= 0.25 (here
     x = 0.1875 with either sign of kappa, 0.25 exactly at Nt = 96, where the polynomial's error
     bound is largest) and by the transforms above it (x = 0.75, 1.5), and the forced fused path
     always by the transforms.  Every entry of M and M^dag of both, with mu != 0 (e^{delta mu}
