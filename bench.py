@@ -340,6 +340,9 @@ def main() -> int:
                     help="CG iterations to time on the unscaled prior field (0: skip)")
     ap.add_argument("--probe", action="store_true",
                     help="only run 20 FP32 operator launches and a 64 MiB copy (for counter runs)")
+    ap.add_argument("--probe-cg", action="store_true",
+                    help="only run 60 mixed CG iterations at L = 51, Nt = 128 (one rhs) and at L = 102, "
+                         "Nt = 192 (four rhs) on the weak field, and a 64 MiB copy (for counter runs)")
     ap.add_argument("--copy-floor", action="store_true",
                     help="only time plain device-to-device copies (HIP graphs) moving the bytes of one "
                          "FP32 / FP64 operator application and larger sizes, one JSON line")
@@ -374,6 +377,23 @@ def main() -> int:
         for h in (hub, hub_lin, hub_tr):        # polynomial stencil, linear stencil, transforms
             for _ in range(20):
                 h.apply_M_c64(P32, V32, out=out32)
+        a = torch.full((16 * 1024 * 1024,), 1.0, dtype=torch.float32, device=dev)   # 64 MiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("probe done")
+        return 0
+    if args.probe_cg:
+        from workloads import STRESS, draw_weak_field
+        for wl, n in ((w, 1), (STRESS, STRESS.nrhs)):
+            pw, cw = draw_weak_field(wl, nrhs=n)
+            hub = Hubbard(wl.L, wl.Nt, wl.beta, wl.kappa, nrhs_max=n, device=dev)
+            r = hub.cg_solve(torch.from_numpy(pw).to(dev), torch.from_numpy(cw).to(dev), tol=1e-10,
+                             prec="mixed", max_iter=60, raise_on_error=False)
+            torch.cuda.synchronize()
+            print(f"{wl.name}: {n} rhs, {max(r.iters)} mixed CG iterations", flush=True)
+            hub.close()
         a = torch.full((16 * 1024 * 1024,), 1.0, dtype=torch.float32, device=dev)   # 64 MiB
         b = torch.empty_like(a)
         for _ in range(5):

@@ -31,10 +31,27 @@ struct RedArgs {
     int nrhs;
 };
 
+// Sum of a wave's 64 values in a fixed order, returned to every lane: each row of 16 lanes is
+// summed into its lane 15 by DPP right shifts, the rows are combined into lane 63 by DPP row
+// broadcasts, and lane 63's value is read back as a scalar.  Every lane must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move_f64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move_f64<0x111, 0xf>(v);            // row_shr:1
+    v += dpp_move_f64<0x112, 0xf>(v);            // row_shr:2
+    v += dpp_move_f64<0x114, 0xf>(v);            // row_shr:4
+    v += dpp_move_f64<0x118, 0xf>(v);            // row_shr:8 (lane 15 of a row: the row's sum)
+    v += dpp_move_f64<0x142, 0xa>(v);            // row_bcast:15 into rows 1 and 3
+    v += dpp_move_f64<0x143, 0xc>(v);            // row_bcast:31 into rows 2 and 3 (lane 63: the sum)
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // Block-wide sum in a fixed order (result valid in thread 0).
@@ -62,23 +79,33 @@ __device__ __forceinline__ double block_allsum(double v, double* lds) {
 }
 
 
-// K sums of `n` partials each, in slot order, returned to every thread: all loads are
-// issued before the first is used and the K block reductions share one pair of barriers.
-// Every block of a kernel forms the same sums (the order depends only on blockDim).
-// `lds` needs K * (waves per block) doubles.
+// K sums of `n` partials each, returned to every thread, in a fixed order.  Up to
+// kWaveSlots partials every wave forms the sums on its own (lane l adds slots l, l + 64,
+// l + 128, ... in turn, then the wave sum): no LDS traffic and one barrier.  Above that thread
+// t adds slots t, t + blockDim, ... and the wave sums meet in LDS (the order then depends on
+// blockDim, the same in every block of a kernel).  Either way every block of a kernel forms the
+// same sums.  Ends with a barrier, as callers may rely on.  `lds` needs K * (waves per block)
+// doubles.
+constexpr int kPartialsPerLane = 4;
+constexpr int kWaveSlots = 64 * kPartialsPerLane;
+
+// the first slot a thread adds and the stride to its next
+__device__ __forceinline__ int2 partial_walk(int n) {
+    return n <= kWaveSlots ? make_int2((int)threadIdx.x & 63, 64) : make_int2((int)threadIdx.x, (int)blockDim.x);
+}
+
 template <int K>
-__device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], int n, double* lds, double (&out)[K]) {
-    double v[K];
+__device__ __forceinline__ void finish_partials(int n, double (&v)[K], double* lds, double (&out)[K]) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (n <= kWaveSlots) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += p[k][j];
+        for (int k = 0; k < K; ++k) out[k] = v[k];
+        __syncthreads();
+        return;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
     __syncthreads();
     if (lane == 0) {
 #pragma unroll
@@ -94,13 +121,26 @@ __device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], int 
     __syncthreads();
 }
 
-// The first partial of each of K arrays that this thread sums (slot threadIdx.x, clamped into
+template <int K>
+__device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], int n, double* lds, double (&out)[K]) {
+    const int2 w = partial_walk(n);
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int j = w.x; j < n; j += w.y) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += p[k][j];
+    }
+    finish_partials<K>(n, v, lds, out);
+}
+
+// The first kPartialsPerLane partials of each of K arrays that this thread adds (clamped into
 // range), loaded ahead of a kernel's other global loads: the memory counter is waited on in
 // issue order, so partials loaded after the prefetch of the operands would make every wave wait
 // for all of those before it could form the CG scalars.
 template <int K>
 struct PartialsPre {
-    double v[K];
+    double v[K][kPartialsPerLane];
     double tol2;                 // and the right-hand side's state, from the scalars
     int done, nonfinite, iters;
 };
@@ -109,9 +149,11 @@ template <int K>
 __device__ __forceinline__ PartialsPre<K> prefetch_partials(const double* const (&p)[K], int n,
                                                             const CgScalars& s) {
     PartialsPre<K> r;
-    const int j = min((int)threadIdx.x, n - 1);
+    const int2 w = partial_walk(n);
 #pragma unroll
-    for (int k = 0; k < K; ++k) r.v[k] = p[k][j];
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int i = 0; i < kPartialsPerLane; ++i) r.v[k][i] = p[k][min(w.x + w.y * i, n - 1)];
     r.tol2 = s.tol2;
     r.done = s.done;
     r.nonfinite = s.nonfinite;
@@ -119,34 +161,25 @@ __device__ __forceinline__ PartialsPre<K> prefetch_partials(const double* const 
     return r;
 }
 
-// sum_partials_k with each thread's first partial already loaded (same order, same sums).
+// sum_partials_k with each thread's first partials already loaded (same order, same sums).
 template <int K>
 __device__ __forceinline__ void sum_partials_pre(const double* const (&p)[K], int n, const PartialsPre<K>& pre,
                                                  double* lds, double (&out)[K]) {
+    const int2 w = partial_walk(n);
     double v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = (int)threadIdx.x < n ? pre.v[k] : 0.0;
-    for (int j = threadIdx.x + blockDim.x; j < n; j += blockDim.x) {
+    for (int k = 0; k < K; ++k) {
+        double a = 0.0;
+#pragma unroll
+        for (int i = 0; i < kPartialsPerLane; ++i)
+            if (w.x + w.y * i < n) a += pre.v[k][i];
+        v[k] = a;
+    }
+    for (int j = w.x + w.y * kPartialsPerLane; j < n; j += w.y) {
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] += p[k][j];
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) lds[wave * K + k] = v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += lds[w * K + k];
-        out[k] = s;
-    }
-    __syncthreads();
+    finish_partials<K>(n, v, lds, out);
 }
 
 struct NoCtlPre {};
