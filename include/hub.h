@@ -78,10 +78,11 @@ typedef enum {
 typedef enum { HUB_PREC_FP64 = 0, HUB_PREC_MIXED = 1 } hub_prec;
 
 /* Which kernel layout applies E: AUTO picks the fused one-slice-per-workgroup
- * kernel when a slice fits in LDS, else the three-kernel split path, and at L = 51 with
- * 3 |delta kappa| <= 0.25 the polynomial stencil for the FP32 operators (see
- * hub_apply_M_c64).  FUSED and SPLIT force one (FUSED fails with HUB_ERR_ARG when the slice
- * does not fit); both apply E through the transforms in both precisions. */
+ * kernel when a slice fits in LDS, else the three-kernel split path, and at L = 51 or 102 with
+ * 3 |delta kappa| <= 0.25 the polynomial stencil for the FP32 operators (see hub_apply_M_c64),
+ * at L = 102 for the FP64 ones too where its bound allows (see hub_apply_M).  FUSED and SPLIT
+ * force one (FUSED fails with HUB_ERR_ARG when the slice does not fit); both apply E through
+ * the transforms in both precisions. */
 typedef enum { HUB_PATH_AUTO = 0, HUB_PATH_FUSED = 1, HUB_PATH_SPLIT = 2 } hub_path;
 
 /* Which fermion matrix the context applies (see the top of this file). */
@@ -137,7 +138,12 @@ void hub_destroy(hub_ctx* ctx);
 
 /* out = M[phi] in  (Sec. 2, eq. "ferm_op", in the context's form), FP64.
  * in and out: complex128 [nrhs][Nt][V]; out may overlap neither in nor phi (HUB_ERR_ARG).
- * 1 <= nrhs <= nrhs_max. */
+ * 1 <= nrhs <= nrhs_max.  With HUB_PATH_AUTO at L = 102 E is applied as e^{delta mu}
+ * p(delta kappa K), p the degree-9 truncated Chebyshev series of e^z on [-3|delta kappa|,
+ * 3|delta kappa|], when its error bound is at most 4e-17 (2.9e-17 at 3|delta kappa| = 0.1875,
+ * below FP64 rounding); otherwise, and at every other L, through the per-slice transforms.
+ * The same holds for every FP64 operator of the context (hub_apply_Mdag, the FP64 steps of
+ * hub_cg_solve, hub_force and the slab variants). */
 hub_status hub_apply_M(hub_ctx* ctx, const double* phi, const void* in, void* out,
                        int32_t nrhs, void* stream);
 
@@ -150,8 +156,8 @@ hub_status hub_apply_Mdag(hub_ctx* ctx, const double* phi, const void* in, void*
  * 3 |delta kappa| <= 0.25 they apply E = e^{delta mu} exp(delta kappa K) (Sec. 2, eq.
  * "ferm_op") as e^{delta mu} p(delta kappa K), p the degree-5 truncated Chebyshev series of e^z on
  * [-3|delta kappa|, 3|delta kappa|] (K's spectrum lies in [-3, 3]), an error of at most 1.1e-8
- * relative, below FP32 rounding; otherwise, and in every FP64 entry point, through the
- * per-slice transforms. */
+ * relative, below FP32 rounding; otherwise through the per-slice transforms (for the FP64
+ * entry points see hub_apply_M). */
 hub_status hub_apply_M_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,
                            int32_t nrhs, void* stream);
 hub_status hub_apply_Mdag_c64(hub_ctx* ctx, const float* phi, const void* in, void* out,

@@ -20,18 +20,30 @@ constexpr double kOmelyanLambda = 0.1931833275037836;
 constexpr int kHalfBelow = 256;     // two workgroups per slice below this many slices
 // FP32 operators at L = 51 and 102 by a degree-5 polynomial of delta kappa K (exp_poly_ratios: the
 // Chebyshev series of e^z on [-x, x], x = 3 |delta kappa|, truncated) while x <= 0.25 and its error
-// bound is at most kPolyTol (1.1e-8 at x = 0.25, 1.9e-9 at the paper's x = 0.1875), a sixth of
-// FP32's unit roundoff or less; larger steps, and every FP64 operator, take the FFT kernels (an
-// FP64 stencil of degree 9, four workgroups per slice, measured 21.4 us per application at L = 51
-// against 17.9 us for the FP64 transforms).  The degree-6 Taylor polynomial reaches the same
-// accuracy with one sweep more (5-8 % slower).  Two workgroups per slice split the 51 columns,
-// four the 102 (each range plus its halos fits 32 lanes); 512 threads: 16 strips of 3-4 rows
-// (L = 51; 768 and 1024 measured slower in CG) or 6-7 rows (L = 102)
+// bound is at most kPolyTol (1.1e-8 at x = 0.25, 1.9e-9 at the paper's x = 0.1875), a third of
+// FP32's unit roundoff or less; larger steps take the FFT kernels.  The degree-6 Taylor polynomial
+// reaches the same accuracy with one sweep more (5-8 % slower).  Two workgroups per slice split
+// the 51 columns, four the 102 (each range plus its halos fits 32 lanes); 512 threads: 16 strips
+// of 3-4 rows (L = 51; 768 and 1024 measured slower in CG) or 6-7 rows (L = 102).
+// FP64 operators at L = 102 by the degree-9 series (2.9e-17 at x = 0.1875; kPolyTol64 is a third
+// of FP64's unit roundoff), six workgroups per slice (17 columns and 5 halos a side fit 32 lanes):
+// there the transforms need the three-kernel split path.  At L = 51 the FP64 stencil (four
+// workgroups per slice) measured 21.4 us per application against 17.9 us for the in-LDS
+// transforms, so FP64 at L = 51 keeps those.
 constexpr double kPolyMaxX = 0.25;
 constexpr int kPolyDeg = 5;
 constexpr double kPolyTol = 2e-8;
+constexpr int kPolyDeg64 = 9;
+constexpr double kPolyTol64 = 4e-17;
 constexpr int kThreadsPoly = 512;
-constexpr int poly_split(int L) { return L == 51 ? 2 : 4; }
+template <typename R>
+constexpr int poly_deg() { return sizeof(R) == sizeof(float) ? kPolyDeg : kPolyDeg64; }
+template <typename R>
+constexpr int poly_split(int L) { return sizeof(R) == sizeof(double) ? 6 : (L == 51 ? 2 : 4); }
+// row groups: FP64 holds 4 rows per lane in two groups of 51 rows and 5 halos a side (7 rows per
+// lane, all 102 rows in one group, spilled in the CG kernels)
+template <typename R>
+constexpr int poly_rsplit(int) { return sizeof(R) == sizeof(double) ? 2 : 1; }
 
 thread_local char g_err[512] = "";
 
@@ -169,6 +181,7 @@ OpKind op_kind(const hub_ctx* c, int nrhs) {
     // that kernel
     if (c->specialized && c->poly && sizeof(R) == sizeof(float) && !(c->L == 102 && c->persist_mode))
         return OpKind::Poly;
+    if (c->specialized && c->poly64 && sizeof(R) == sizeof(double)) return OpKind::Poly;
     if (c->path == HUB_PATH_SPLIT) {
         if (!c->split_forced && c->specialized && c->L == 102 && sizeof(R) == sizeof(float)) return OpKind::Sub102;
         return OpKind::Split;
@@ -181,7 +194,7 @@ template <typename R>
 int op_slots(const hub_ctx* c, int nrhs) {
     switch (op_kind<R>(c, nrhs)) {
         case OpKind::Half51: return 2 * c->Nt;
-        case OpKind::Poly: return poly_split(c->L) * c->Nt;
+        case OpKind::Poly: return poly_split<R>(c->L) * poly_rsplit<R>(c->L) * c->Nt;
         case OpKind::Split: return 2 * c->Nt * split_geom(c->L).nrb;
         case OpKind::Linear: return c->Nt * lin_nch(c, nrhs);
         default: return c->Nt;
@@ -213,6 +226,17 @@ hub_status run_split_ct(hub_ctx* c, int nrhs, const OpTab<R>& T, const Src& src,
     return launch_check("k_split_rows_inv_ct");
 }
 
+// The polynomial stencil at a compile-time L: poly_split<R>(L) x poly_rsplit<R>(L) workgroups
+// per slice.
+template <typename R, int L, class Src, class Epi, class Ctl>
+hub_status launch_poly(const hub_ctx* c, int nrhs, const OpTab<R>& T, const PolyCoef<R>& pc, const Src& src,
+                       const Epi& epi, const Ctl& ctl, hipStream_t st) {
+    constexpr int NS = poly_split<R>(L), RS = poly_rsplit<R>(L);
+    auto kern = k_exp_poly<R, L, kThreadsPoly, poly_deg<R>(), NS, RS, Src, Epi, Ctl>;
+    hipLaunchKernelGGL(kern, dim3(NS * RS * nrhs * c->Nt), dim3(kThreadsPoly), 0, st, T, pc, src, epi, ctl);
+    return launch_check(L == 51 ? "k_exp_poly<51>" : "k_exp_poly<102>");
+}
+
 // Apply E between a source functor and an epilogue functor over nrhs right-hand sides.
 template <typename R, class Src, class Epi, class Ctl>
 hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ctl& ctl_in, hipStream_t st) {
@@ -238,22 +262,16 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
             return launch_check("k_fused_ct<51, half>");
         }
         case OpKind::Poly: {
-            if constexpr (sizeof(R) == sizeof(float)) {
-                PolyCoef<R> pc{};
-                pc.scale = (R)(std::exp(c->delta * c->mu) * c->poly_a0);
-                for (int k = 1; k <= kPolyDeg; ++k) pc.c[k] = (R)(c->delta * c->kappa * c->poly_ratio[k]);
-                if (c->L == 51) {
-                    auto kern = k_exp_poly<R, 51, kThreadsPoly, kPolyDeg, poly_split(51), Src, Epi, Ctl>;
-                    hipLaunchKernelGGL(kern, dim3(poly_split(51) * nrhs * c->Nt), dim3(kThreadsPoly), 0, st, T, pc,
-                                       src, epi, ctl);
-                    return launch_check("k_exp_poly<51>");
-                }
-                auto kern = k_exp_poly<R, 102, kThreadsPoly, kPolyDeg, poly_split(102), Src, Epi, Ctl>;
-                hipLaunchKernelGGL(kern, dim3(poly_split(102) * nrhs * c->Nt), dim3(kThreadsPoly), 0, st, T, pc,
-                                   src, epi, ctl);
-                return launch_check("k_exp_poly<102>");
+            constexpr bool f32 = sizeof(R) == sizeof(float);
+            PolyCoef<R> pc{};
+            pc.scale = (R)(std::exp(c->delta * c->mu) * (f32 ? c->poly_a0 : c->poly64_a0));
+            for (int k = 1; k <= poly_deg<R>(); ++k)
+                pc.c[k] = (R)(c->delta * c->kappa * (f32 ? c->poly_ratio[k] : c->poly64_ratio[k]));
+            if constexpr (f32) {
+                if (c->L == 51) return launch_poly<R, 51>(c, nrhs, T, pc, src, epi, ctl, st);
             }
-            return fail(HUB_ERR_ARG, "internal: the polynomial stencil is FP32 only");
+            if (c->L != 102) return fail(HUB_ERR_ARG, "internal: no polynomial stencil at L = %d", c->L);
+            return launch_poly<R, 102>(c, nrhs, T, pc, src, epi, ctl, st);
         }
         case OpKind::Whole51: {
             auto kern = k_fused_ct<R, 51, kThreads51, false, Src, Epi, Ctl>;
@@ -817,6 +835,10 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
         if (!lin && prm->path == HUB_PATH_AUTO && (c->L == 51 || c->L == 102) && x <= kPolyMaxX) {
             c->poly_err = exp_poly_ratios(x, kPolyDeg, &c->poly_a0, c->poly_ratio);
             c->poly = c->poly_err >= 0.0 && c->poly_err <= kPolyTol;
+            if (c->L == 102) {
+                c->poly64_err = exp_poly_ratios(x, kPolyDeg64, &c->poly64_a0, c->poly64_ratio);
+                c->poly64 = c->poly64_err >= 0.0 && c->poly64_err <= kPolyTol64;
+            }
         }
     }
 
@@ -845,6 +867,7 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     const SplitGeom G = split_geom(c->L);
     c->max_partials = std::max(2 * c->Nt, c->Nt * 2 * G.nrb);
     c->max_partials = std::max(c->max_partials, c->Nt * lin_nch(c, 1));
+    c->max_partials = std::max(c->max_partials, c->Nt * poly_split<double>(c->L) * poly_rsplit<double>(c->L));
     CREATE_OR_BAIL(hipMalloc(&c->partials, (size_t)c->nrhs_max * c->max_partials * sizeof(double)));
     CREATE_OR_BAIL(hipMalloc(&c->counters, kNumCounters * sizeof(unsigned int)));
     CREATE_OR_BAIL(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(unsigned int), st));

@@ -45,8 +45,12 @@ struct hub_ctx {
     bool split_forced = false;       // HUB_PATH_SPLIT requested: no fused kernel of any kind
     bool poly = false;               // FP32 operators by the polynomial stencil (HUB_PATH_AUTO, L = 51, 102)
     double poly_a0 = 1.0;            // its polynomial (exp_poly_ratios): a_0, a_k / a_{k-1}, error bound
-    double poly_ratio[9] = {};
+    double poly_ratio[11] = {};
     double poly_err = -1.0;
+    bool poly64 = false;             // FP64 operators by the polynomial stencil (HUB_PATH_AUTO, L = 102)
+    double poly64_a0 = 1.0;          // and its polynomial
+    double poly64_ratio[11] = {};
+    double poly64_err = -1.0;
     int lds_fused64 = 0, lds_fused32 = 0;
     int max_lds = 0;
     hub::FftPlan plan{};

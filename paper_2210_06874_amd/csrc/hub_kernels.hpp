@@ -1105,23 +1105,32 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
 // NSPLIT workgroups per slice split the columns n2: workgroup h writes columns
 // [h L / NSPLIT, (h + 1) L / NSPLIT) and carries H = ceil(DEG/2) halo columns on each side,
 // since each pair of sweeps widens a site's dependence by one column each way (A(n) reaches
-// B(n - e2), B(m) reaches A(m + e2)).
+// B(n - e2), B(m) reaches A(m + e2)).  RSPLIT > 1 splits the rows n1 the same way: a workgroup
+// holds its group's rows and H halo rows above and below, with no wrap inside the workgroup
+// (the rows beyond the halos read as 0; after DEG sweeps the values they spoil reach at most
+// H - 1 rows inward, all halo rows, which are never written).  RSPLIT = 1 holds all L rows,
+// periodic.  Fewer rows per lane hold fewer registers (FP64), at the cost of the halo rows.
 // Lanes run along n2 (32 lanes per strip when the columns and halos fit, so a strip is half a
 // wave, else 64; a site's n2 neighbours are the adjacent lanes, fetched with wave-wide DPP
 // shifts, and the lanes at a strip's two edges receive another strip's values or 0, which only
-// ever feed halo columns).  FP32 only: in FP64 (degree 9 or 12, each double crossing lanes as two
-// 32-bit shifts that do not fold into the adds) the FFT kernels measured faster.  Rows n1 (periodic, all
-// L of them) are split into NT/32 strips of at most RMAX rows held in registers; the row above
-// and below a strip cross strips through LDS once per sweep.
-template <int L, int NT, int DEG, int NSPLIT>
+// ever feed halo columns).  In FP64 (degree 9) each double crosses lanes as two 32-bit shifts
+// that do not fold into the adds; there the kernel is used at L = 102 only, where the transforms
+// need the three-kernel split path (at L = 51 the in-LDS transforms measured faster).  Rows n1
+// (periodic, all L of them) are split into NT/32 strips of at most RMAX rows held in registers;
+// the row above and below a strip cross strips through LDS once per sweep.
+template <int L, int NT, int DEG, int NSPLIT, int RSPLIT>
 struct PolyGeom {
     static constexpr int H = (DEG + 1) / 2;
     static constexpr int W = (L + NSPLIT - 1) / NSPLIT + 2 * H;   // widest column range with its halos
     static constexpr int LPS = W <= 32 ? 32 : 64;        // lanes (columns) per strip
     static constexpr int NSTRIP = NT / LPS;
-    static constexpr int RMAX = (L + NSTRIP - 1) / NSTRIP;
+    // rows held: all L, or the widest row group with its halos (the narrowest has one row fewer)
+    static constexpr int VR = RSPLIT == 1 ? L : (L + RSPLIT - 1) / RSPLIT + 2 * H;
+    static constexpr int RMAX = (VR + NSTRIP - 1) / NSTRIP;
     static_assert(W <= LPS, "column range and halos must fit one strip");
     static_assert(NT % 64 == 0, "whole waves");
+    static_assert(RSPLIT == 1 || VR <= L, "a row group's halos must not wrap onto its own rows");
+    static_assert(VR - 1 >= NSTRIP, "every strip holds a row");
 };
 
 // Wave-wide lane shifts (DPP): lane i receives lane i - 1 (prev) or i + 1 (next); the lane
@@ -1138,32 +1147,53 @@ __device__ __forceinline__ cx<float> lane_prev(cx<float> v) {
 __device__ __forceinline__ cx<float> lane_next(cx<float> v) {
     return {lane_shift<kDppWaveShl1>(v.re), lane_shift<kDppWaveShl1>(v.im)};
 }
+// a double moves as its two 32-bit halves
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ cx<double> lane_prev(cx<double> v) {
+    return {lane_shift<kDppWaveShr1>(v.re), lane_shift<kDppWaveShr1>(v.im)};
+}
+__device__ __forceinline__ cx<double> lane_next(cx<double> v) {
+    return {lane_shift<kDppWaveShl1>(v.re), lane_shift<kDppWaveShl1>(v.im)};
+}
 
-// The polynomial's constants: c[j] = delta kappa a_j / a_{j-1} for sweep j = 1..8, and the final
+// The polynomial's constants: c[j] = delta kappa a_j / a_{j-1} for sweep j = 1..10, and the final
 // scale e^{delta mu} a_0.
 template <typename R>
 struct PolyCoef {
     R scale;
-    R c[9];
+    R c[11];
 };
 
-template <typename R, int L, int NT, int DEG, int NSPLIT, class Src, class Epi, class Ctl>
+template <typename R, int L, int NT, int DEG, int NSPLIT, int RSPLIT, class Src, class Epi, class Ctl>
 __global__ void __launch_bounds__(NT)
 k_exp_poly(const OpTab<R> T, const PolyCoef<R> pc, const Src src, const Epi epi, const Ctl ctl) {
-    static_assert(sizeof(R) == sizeof(float), "FP32 only: in FP64 the FFT kernels measured faster");
-    static_assert(DEG >= 1 && DEG <= 8, "c[] holds eight sweeps");
-    using G = PolyGeom<L, NT, DEG, NSPLIT>;
-    constexpr int LL = L * L, RM = G::RMAX, NS = G::NSTRIP;
+    static_assert(DEG >= 1 && DEG <= 10, "c[] holds ten sweeps");
+    using G = PolyGeom<L, NT, DEG, NSPLIT, RSPLIT>;
+    constexpr int LL = L * L, RM = G::RMAX, NS = G::NSTRIP, PARTS = NSPLIT * RSPLIT;
     __shared__ cx<R> edgeA[2][NS][G::LPS];               // first row's A of each strip, per sweep parity
     __shared__ cx<R> edgeB[2][NS][G::LPS];               // last row's B
     __shared__ double red_lds[64];
     const int u = xcd_linear(blockIdx.x, gridDim.x);
-    const int q = u / NSPLIT, h = u - q * NSPLIT;
+    const int q = u / PARTS, part = u - q * PARTS;
+    const int h = part % NSPLIT, g = part / NSPLIT;      // column range, row group
     const int rhs = q / T.Nt, t = q - rhs * T.Nt;
-    const int slot = NSPLIT * t + h;
+    const int slot = PARTS * t + part;
     const int tid = threadIdx.x;
     const int s = tid / G::LPS, j = tid - s * G::LPS;
-    const int r0 = s * L / NS, nr = (s + 1) * L / NS - r0;
+    // rows held: rows v in [0, nv) are global rows vbase + v (mod L); those written are [vo0, vo0 + NR)
+    const int R0 = g * L / RSPLIT, NR = (g + 1) * L / RSPLIT - R0;
+    const int nv = RSPLIT == 1 ? L : NR + 2 * G::H;
+    const int vbase = RSPLIT == 1 ? 0 : R0 - G::H + L;
+    const int vo0 = RSPLIT == 1 ? 0 : G::H;
+    const int r0 = s * nv / NS, nr = (s + 1) * nv / NS - r0;
+    auto grow = [&](int v) { return RSPLIT == 1 ? v : (vbase + v) % L; };
+    auto out_row = [&](int r) { return r < nr && r0 + r >= vo0 && r0 + r < vo0 + NR; };
     const int c0 = h * L / NSPLIT, ncol = (h + 1) * L / NSPLIT - c0;
     const int n2 = (c0 - G::H + j + L) % L;
     const bool out_lane = j >= G::H && j < G::H + ncol;
@@ -1174,7 +1204,7 @@ k_exp_poly(const OpTab<R> T, const PolyCoef<R> pc, const Src src, const Epi epi,
     typename Src::Pre pa[RM], pb[RM];
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-        const int n1 = r0 + min(r, nr - 1);                // rows past the strip repeat its last row
+        const int n1 = grow(r0 + min(r, nr - 1));          // rows past the strip repeat its last row
         pa[r] = src.fetch(rhs, ts, n1 * L + n2, T);
         pb[r] = src.fetch(rhs, ts, LL + n1 * L + n2, T);
     }
@@ -1187,9 +1217,9 @@ k_exp_poly(const OpTab<R> T, const PolyCoef<R> pc, const Src src, const Epi epi,
     auto fetch_epi = [&]() {
 #pragma unroll
         for (int r = 0; r < RM; ++r) {
-            if (out_lane && r < nr) {
-                ea[r] = epi.fetch(rhs, t, (r0 + r) * L + n2, T);
-                eb[r] = epi.fetch(rhs, t, LL + (r0 + r) * L + n2, T);
+            if (out_lane && out_row(r)) {
+                ea[r] = epi.fetch(rhs, t, grow(r0 + r) * L + n2, T);
+                eb[r] = epi.fetch(rhs, t, LL + grow(r0 + r) * L + n2, T);
             }
         }
     };
@@ -1199,9 +1229,9 @@ k_exp_poly(const OpTab<R> T, const PolyCoef<R> pc, const Src src, const Epi epi,
         if (out_lane) {
 #pragma unroll
             for (int r = 0; r < RM; ++r)
-                if (r < nr) {
-                    epi_early<R>(epi, rhs, t, (r0 + r) * L + n2, ea[r], T, sc);
-                    epi_early<R>(epi, rhs, t, LL + (r0 + r) * L + n2, eb[r], T, sc);
+                if (out_row(r)) {
+                    epi_early<R>(epi, rhs, t, grow(r0 + r) * L + n2, ea[r], T, sc);
+                    epi_early<R>(epi, rhs, t, LL + grow(r0 + r) * L + n2, eb[r], T, sc);
                 }
         }
     };
@@ -1227,8 +1257,10 @@ k_exp_poly(const OpTab<R> T, const PolyCoef<R> pc, const Src src, const Epi epi,
             edgeA[par][s][j] = ya[0];
             edgeB[par][s][j] = lastb;
             __syncthreads();
-            const cx<R> above = edgeB[par][sp][j];        // B of row r0 - 1 (the previous strip's last)
-            const cx<R> below = edgeA[par][sn][j];        // A of row r0 + nr (the next strip's first)
+            // B of row r0 - 1 (the previous strip's last), A of row r0 + nr (the next strip's
+            // first); with row groups the first strip has nothing above, the last nothing below
+            const cx<R> above = (RSPLIT > 1 && s == 0) ? cx<R>{0, 0} : edgeB[par][sp][j];
+            const cx<R> below = (RSPLIT > 1 && s == NS - 1) ? cx<R>{0, 0} : edgeA[par][sn][j];
             const R ck = pc.c[k];
             // rows top to bottom, in place: row r's new A needs the old B of rows r and r - 1
             // (the latter carried in bup), its new B the old A of rows r and r + 1 (not yet
@@ -1251,9 +1283,9 @@ k_exp_poly(const OpTab<R> T, const PolyCoef<R> pc, const Src src, const Epi epi,
         if (out_lane) {
 #pragma unroll
             for (int r = 0; r < RM; ++r)
-                if (r < nr) {
-                    epi.store(rhs, t, (r0 + r) * L + n2, scale(pc.scale, ya[r]), ea[r], T, sc, acc);
-                    epi.store(rhs, t, LL + (r0 + r) * L + n2, scale(pc.scale, yb[r]), eb[r], T, sc, acc);
+                if (out_row(r)) {
+                    epi.store(rhs, t, grow(r0 + r) * L + n2, scale(pc.scale, ya[r]), ea[r], T, sc, acc);
+                    epi.store(rhs, t, LL + grow(r0 + r) * L + n2, scale(pc.scale, yb[r]), eb[r], T, sc, acc);
                 }
         }
     }

@@ -155,18 +155,18 @@ def _stress_slices(op, phi, v, slices, dagger):
     return out
 
 
-@pytest.mark.parametrize("kernel", ["default", "sublattice"])
+@pytest.mark.parametrize("kernel", ["default", "sublattice", "split"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_apply_stress_workload_sampled(prec, kernel):
     """L = 102, Nt = 192, 4 right-hand sides in one call: sampled slices, including both wrap
-    slices, against the oracle (FP64: split path; FP32: the default polynomial stencil and the
-    sublattice kernel)."""
+    slices, against the oracle (the default polynomial stencil, degree 9 in FP64 and 5 in FP32;
+    the forced split path; the FP32 sublattice kernel)."""
     if prec == "fp64" and kernel == "sublattice":
         pytest.skip("the sublattice kernel is FP32 only")
     w = STRESS
     print(f"[case] apply {prec} {w.name} {kernel}", flush=True)
     phi, v = draw_inputs(w, seed=15)
-    hub = _hub(w, nrhs=4)
+    hub = _hub(w, nrhs=4, path="split" if kernel == "split" else "auto")
     if kernel == "sublattice":
         hub.set_cg_launch(sublattice=True)
     op = oracle_op(w, mode="expm")
@@ -185,6 +185,23 @@ def test_apply_stress_workload_sampled(prec, kernel):
         ref = _stress_slices(op, phi, v, slices, dag)
         for t in slices:
             assert_close_elementwise(got[:, t], ref[t], tol, f"slice {t} dag={dag}")
+
+
+def test_fp64_stencil_and_split_path_agree_at_L102():
+    """The FP64 operators at L = 102 by the degree-9 polynomial stencil (default) and by the
+    split-path transforms, on every entry of 4 right-hand sides: both are E = exp(delta kappa K)
+    to FP64 accuracy (the series' bound is 2.9e-17 at this step, Sec. 2 eq. "ferm_op"), so they
+    agree to the transforms' rounding.  The oracle checks both on sampled slices."""
+    w = STRESS
+    print(f"[case] fp64 stencil vs split {w.name}", flush=True)
+    phi, v = draw_inputs(w, seed=18)
+    P, V = to_dev(phi), to_dev(v)
+    poly, split = _hub(w, nrhs=4), _hub(w, nrhs=4, path="split")
+    for f in ("apply_M", "apply_Mdag"):
+        a = to_np(getattr(poly, f)(P, V))
+        b = to_np(getattr(split, f)(P, V))
+        err = np.abs(a - b).max() / np.abs(b).max()
+        assert err <= 1e-14, (f, err)
 
 
 @pytest.mark.parametrize("w", [PREC, STRESS], ids=lambda w: w.name)
