@@ -307,9 +307,11 @@ hub_status hub_log_det(hub_ctx* ctx, const double* phi, double* out_dev, void* s
  * hub_cg_solve return HUB_ERR_DEVICE with x undefined. */
 hub_status hub_set_cg_launch(hub_ctx* ctx, int32_t persistent, int64_t barrier_spin_limit);
 
-/* Report the kernel path the context uses (hub_path value, never AUTO) and the
- * LDS bytes per workgroup of its operator kernel (HUB_FORM_LINEAR: FUSED and 0, one
- * stencil kernel that uses no dynamic LDS). */
+/* Report the transform layout the context uses (hub_path value, never AUTO) and the
+ * LDS bytes per workgroup of its transform kernel (HUB_FORM_LINEAR: FUSED and 0, one
+ * stencil kernel that uses no dynamic LDS).  Where the polynomial stencil applies E instead
+ * (see hub_apply_M and hub_apply_M_c64) the layout reported is the one the other operators of
+ * the context use. */
 hub_status hub_query(const hub_ctx* ctx, int32_t* path, int32_t* lds_bytes);
 
 /* Thread-local description of the last non-OK status returned on this thread. */

@@ -285,10 +285,12 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
             hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads), lds, st, T, src, epi, ctl);
             return launch_check("k_fused");
         }
-        case OpKind::Split:
         case OpKind::Linear:
+            return fail(HUB_ERR_ARG, "internal: the linear form has its own kernels");
+        case OpKind::Split:
             break;
     }
+    if (!c->split_w) return fail(HUB_ERR_ARG, "internal: split path without its scratch vector");
     if (c->specialized && c->L == 102) {
         constexpr SplitGeom G102 = split_geom(102);
         static_assert(102 % G102.rb == 0 && 102 % G102.cb == 0, "tiles must divide L");
@@ -872,7 +874,9 @@ hub_status hub_create(const hub_params* prm, void* stream, hub_ctx** out) {
     CREATE_OR_BAIL(hipMalloc(&c->counters, kNumCounters * sizeof(unsigned int)));
     CREATE_OR_BAIL(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(unsigned int), st));
     CREATE_OR_BAIL(hipMalloc(&c->red_out, 8 * sizeof(double)));
-    if (c->path == HUB_PATH_SPLIT && !lin)
+    // the split path's scratch vector, unless the stencils take every operator (then FP64 runs the
+    // polynomial stencil, FP32 that or the sublattice kernel)
+    if (c->path == HUB_PATH_SPLIT && !lin && !c->poly64)
         CREATE_OR_BAIL(hipMalloc(&c->split_w, (size_t)c->nrhs_max * c->N * sizeof(cx<double>)));
     // per-right-hand-side forces before their sum (exponential form, nrhs > 1)
     if (c->nrhs_max > 1 && !lin)

@@ -477,18 +477,22 @@ def test_context_manager_releases_the_context():
     assert torch.isfinite(ref.real).all()
 
 
-@pytest.mark.parametrize("L,Nt,nrhs,path", [(51, 255, 1, "auto"), (51, 127, 2, "auto"), (51, 60, 4, "auto"),
-                                            (51, 1, 1, "auto"), (51, 3, 3, "auto"), (51, 255, 1, "fused"),
-                                            (51, 127, 2, "fused"), (51, 60, 4, "fused"), (51, 1, 1, "fused"),
-                                            (51, 3, 3, "fused"), (102, 5, 3, "auto"), (102, 1, 2, "auto")])
-def test_production_lengths_at_odd_shapes(L, Nt, nrhs, path):
+@pytest.mark.parametrize("L,Nt,nrhs,path,delta", [
+    (51, 255, 1, "auto", 0.0625), (51, 127, 2, "auto", 0.0625), (51, 60, 4, "auto", 0.0625),
+    (51, 1, 1, "auto", 0.0625), (51, 3, 3, "auto", 0.0625), (51, 255, 1, "fused", 0.0625),
+    (51, 127, 2, "fused", 0.0625), (51, 60, 4, "fused", 0.0625), (51, 1, 1, "fused", 0.0625),
+    (51, 3, 3, "fused", 0.0625), (102, 5, 3, "auto", 0.0625), (102, 1, 2, "auto", 0.0625),
+    (102, 3, 2, "auto", 0.08), (102, 2, 1, "auto", 0.1)])
+def test_production_lengths_at_odd_shapes(L, Nt, nrhs, path, delta):
     """The compile-time L = 51 and L = 102 kernels on both sides of the two-workgroup switch
     (fewer than 256 slices), with several right-hand sides, a single slice and odd N_t: M, M^dag,
     FP32 M and M^dag and the force on sampled slices against the oracle's Krylov route (at
-    L = 51 FP32 both the polynomial-stencil kernel of the default path and the transform kernels)."""
+    L = 51 FP32 both the polynomial-stencil kernel of the default path and the transform kernels).
+    At L = 102 the step delta = 1/16 runs both polynomial stencils; 0.08 (3 delta kappa = 0.24) keeps
+    the FP32 one and sends FP64 to the split path; 0.1 sends FP32 to the sublattice kernel too."""
     from paper_2210_06874_amd import Hubbard
-    print(f"[case] production length L={L} Nt={Nt} nrhs={nrhs} path={path}", flush=True)
-    w = Lattice(f"L{L}_Nt{Nt}", L, Nt, 0.0625 * Nt, 3.9, nrhs=nrhs)
+    print(f"[case] production length L={L} Nt={Nt} nrhs={nrhs} path={path} delta={delta}", flush=True)
+    w = Lattice(f"L{L}_Nt{Nt}", L, Nt, delta * Nt, 3.9, nrhs=nrhs)
     phi, v = draw_inputs(w, seed=L + Nt, nrhs=nrhs)
     op = oracle_op(w, mode="expm")
     hub = Hubbard(L, Nt, w.beta, w.kappa, nrhs_max=nrhs, path=path)
