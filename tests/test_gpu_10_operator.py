@@ -187,21 +187,28 @@ def test_apply_stress_workload_sampled(prec, kernel):
             assert_close_elementwise(got[:, t], ref[t], tol, f"slice {t} dag={dag}")
 
 
-def test_fp64_stencil_and_split_path_agree_at_L102():
-    """The FP64 operators at L = 102 by the degree-9 polynomial stencil (default) and by the
-    split-path transforms, on every entry of 4 right-hand sides: both are E = exp(delta kappa K)
-    to FP64 accuracy (the series' bound is 2.9e-17 at this step, Sec. 2 eq. "ferm_op"), so they
-    agree to the transforms' rounding.  The oracle checks both on sampled slices."""
+@pytest.mark.parametrize("mu,kappa", [(0.0, 1.0), (0.3, 1.0), (0.0, -1.0)])
+def test_fp64_stencil_and_split_path_agree_at_L102(mu, kappa):
+    """The FP64 operators and the force at L = 102 by the degree-9 polynomial stencil (default)
+    and by the split-path transforms, on every entry of 4 right-hand sides: both are
+    E = e^{delta mu} exp(delta kappa K) to FP64 accuracy (the series' bound is 2.9e-17 at this
+    step, Sec. 2 eq. "ferm_op"; mu enters as the scale, a negative kappa through the sweeps'
+    coefficients), so they agree to the transforms' rounding.  The oracle checks both on sampled
+    slices at mu = 0, kappa = 1."""
+    from paper_2210_06874_amd import Hubbard
     w = STRESS
-    print(f"[case] fp64 stencil vs split {w.name}", flush=True)
+    print(f"[case] fp64 stencil vs split {w.name} mu={mu} kappa={kappa}", flush=True)
     phi, v = draw_inputs(w, seed=18)
     P, V = to_dev(phi), to_dev(v)
-    poly, split = _hub(w, nrhs=4), _hub(w, nrhs=4, path="split")
-    for f in ("apply_M", "apply_Mdag"):
+    poly = Hubbard(w.L, w.Nt, w.beta, kappa, nrhs_max=4, mu=mu)
+    split = Hubbard(w.L, w.Nt, w.beta, kappa, nrhs_max=4, mu=mu, path="split")
+    for f in ("apply_M", "apply_Mdag", "force"):
         a = to_np(getattr(poly, f)(P, V))
         b = to_np(getattr(split, f)(P, V))
         err = np.abs(a - b).max() / np.abs(b).max()
         assert err <= 1e-14, (f, err)
+    poly.close()
+    split.close()
 
 
 @pytest.mark.parametrize("w", [PREC, STRESS], ids=lambda w: w.name)
