@@ -267,8 +267,9 @@ def stress_leg(dev, steps: int, persistent: bool = True) -> dict:
         dt = time.perf_counter() - t0
         it = max(res.iters)
         cg[mode] = {"us_per_iteration": dt / it * 1e6, "iterations": it,
-                    # 88 B per site-slice reading FP32 angles (the stencil), 96 B with a phase table
-                    "GBs": (88.0 if mode == "two_kernel" else 96.0) * w.N * w.nrhs * it / dt / 1e9,
+                    # 80 B per site-slice on average with the stencil (FP32 angles, x updated every
+                    # other iteration), 96 B with a phase table and x every iteration
+                    "GBs": (80.0 if mode == "two_kernel" else 96.0) * w.N * w.nrhs * it / dt / 1e9,
                     "persistent_launches": res.persistent_launches}
     hub.set_cg_launch(persistent=False)
     return {"workload": f"{w.name}: L={w.L} Nt={w.Nt} beta={w.beta} U={w.U}, {w.nrhs} right-hand sides per launch",
@@ -491,13 +492,14 @@ def main() -> int:
     lin = linear_leg(w, dev, P32, V32, out32, args.steps, args.warmup)
     batching = nrhs_scan(w, dev)
 
-    # the timed step is almost all CG iterations: two operator kernels that move 88 B per
-    # site-slice in FP32 (M^dag step: read r, p, the FP32 angle, write t; update step: read t,
-    # p, x, r, the angle, write p, x, r), from the timed region's own clock
+    # the timed step is almost all CG iterations: two operator kernels that move 80 B per
+    # site-slice in FP32 on average (M^dag step: read r, p, the FP32 angle, write t: 28 B;
+    # update step: read t, p, r, the angle, write p, r, and every other iteration read and write
+    # x for two iterations at once: 44 or 60 B), from the timed region's own clock
     us_it = ms_per_step * 1e3 / last.iters[0]
-    cg_iter = {"alg_bytes_per_iteration": 88.0 * w.N, "us_per_iteration": us_it,
-               "achieved_GBs": 88.0 * w.N / (us_it * 1e-6) / 1e9,
-               "frac_of_hbm_peak": 88.0 * w.N / (us_it * 1e-6) / 1e9 / HBM_PEAK_GBS,
+    cg_iter = {"alg_bytes_per_iteration": 80.0 * w.N, "us_per_iteration": us_it,
+               "achieved_GBs": 80.0 * w.N / (us_it * 1e-6) / 1e9,
+               "frac_of_hbm_peak": 80.0 * w.N / (us_it * 1e-6) / 1e9 / HBM_PEAK_GBS,
                "note": "wall time of the timed steps over their CG iterations (includes the force, "
                        "action and reliable updates, about 3 %)"}
 

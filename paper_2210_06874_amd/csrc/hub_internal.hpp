@@ -29,7 +29,8 @@ struct CgScalars {
     int32_t iters;
     int32_t reliable;
     int32_t nonfinite;
-    int32_t pad;
+    int32_t x_pending;   // paired x updates: the last iteration left alpha_prev * p for x
+    double alpha_prev;   // that iteration's alpha
 };
 
 }  // namespace hub

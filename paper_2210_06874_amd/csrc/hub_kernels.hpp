@@ -189,6 +189,8 @@ struct NoCtlPre {};
 struct Scal {
     int open;
     double alpha, beta;
+    double alpha_prev = 0.0;     // paired x updates (EpiUpdate kXPair): the previous iteration's alpha
+    int pending = 0;             // and whether its alpha_prev * p is still to be added to x
 };
 
 // Store this block's partial, and let the block that arrives last sum every right-hand
@@ -329,6 +331,18 @@ struct EpiHasEarly : std::false_type {};
 template <class Epi>
 struct EpiHasEarly<Epi, std::void_t<decltype(Epi::kEarly)>> : std::bool_constant<Epi::kEarly> {};
 
+// epilogues with a step for blocks that do no work (EpiUpdate's pending x term)
+template <class Epi, class = void>
+struct EpiHasClosed : std::false_type {};
+template <class Epi>
+struct EpiHasClosed<Epi, std::void_t<decltype(&Epi::closed)>> : std::true_type {};
+
+// the x-update form of an epilogue (EpiUpdate's kXMode), kXPlain for every other
+template <class Epi, class = void>
+struct EpiXMode : std::integral_constant<int, 0> {};
+template <class Epi>
+struct EpiXMode<Epi, std::void_t<decltype(Epi::kXMode)>> : std::integral_constant<int, Epi::kXMode> {};
+
 template <typename R, class Epi>
 __device__ __forceinline__ void epi_early(const Epi& epi, int rhs, int t, int i, typename Epi::Pre& a,
                                           const OpTab<R>& T, const Scal& sc) {
@@ -398,25 +412,53 @@ template <typename R>
 struct PreUpdate {
     cx<R> tq, p, x, r;
 };
-
 template <typename R>
+struct PreUpdateNoX {
+    cx<R> tq, p, r;
+};
+
+// How the CG update step treats x (the update x_{i+1} = x_i + alpha_i p_i).  Plain: every
+// iteration.  Paired: an even iteration of a block skips x (it leaves alpha_i p_i pending and
+// keeps alpha_i in the scalars) and the odd one after it adds both terms, alpha_i p_i +
+// alpha_{i+1} p_{i+1}, from the p_i it reads and the p_{i+1} it forms: x is read and written
+// every other iteration, 16 of the step's 60 bytes per site-slice.  A right-hand side that falls
+// idle after a skip adds its pending term in the next (paired) step; the host gives the last
+// iteration of an odd-length block the plain form, so no term is pending at a reliable update.
+constexpr int kXPlain = 0, kXSkip = 1, kXPair = 2;
+
+template <typename R, int XM = kXPlain>
 struct EpiUpdate {               // CG: p = r + beta p; x += alpha p (early); q = tv_t - B_t w; r -= alpha q; acc |r|^2
-    using Pre = PreUpdate<R>;
+    using Pre = std::conditional_t<XM == kXSkip, PreUpdateNoX<R>, PreUpdate<R>>;
     static constexpr bool kEarly = true;
+    static constexpr int kXMode = XM;
     const cx<R>* tv;
     cx<R>* p;
     cx<R>* x;
     cx<R>* r;
     __device__ Pre fetch(int rhs, int t, int i, const OpTab<R>& T) const {
         const long long k = rhs * T.N + (long long)t * T.V + i;
-        return {tv[k], p[k], x[k], r[k]};
+        if constexpr (XM == kXSkip) return {tv[k], p[k], r[k]};
+        else return {tv[k], p[k], x[k], r[k]};
     }
     __device__ void early(int rhs, int t, int i, Pre& a, const OpTab<R>& T, const Scal& sc) const {
         const long long k = rhs * T.N + (long long)t * T.V + i;
         const R b = (R)sc.beta, al = (R)sc.alpha;
         const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
         p[k] = pn;
-        x[k] = {a.x.re + al * pn.re, a.x.im + al * pn.im};
+        if constexpr (XM == kXPlain) {
+            x[k] = {a.x.re + al * pn.re, a.x.im + al * pn.im};
+        } else if constexpr (XM == kXPair) {
+            const R ap = (R)sc.alpha_prev;
+            x[k] = {fmar(al, pn.re, fmar(ap, a.p.re, a.x.re)), fmar(al, pn.im, fmar(ap, a.p.im, a.x.im))};
+        }
+    }
+    // a paired step of a right-hand side that went idle after the skip: add the pending term
+    __device__ void closed(int rhs, int t, int i, const Pre& a, const OpTab<R>& T, const Scal& sc) const {
+        if constexpr (XM == kXPair) {
+            const long long k = rhs * T.N + (long long)t * T.V + i;
+            const R ap = (R)sc.alpha_prev;
+            x[k] = {fmar(ap, a.p.re, a.x.re), fmar(ap, a.p.im, a.x.im)};
+        }
     }
     __device__ void store(int rhs, int t, int i, cx<R> w, const Pre& a, const OpTab<R>& T, const Scal& sc,
                           double& acc) const {
@@ -770,8 +812,11 @@ struct CtlSearch {
 
 // CG iteration i, second kernel: q = M t, p = r + beta p, x += alpha p, r -= alpha q,
 // alpha = rr_i / ||t||^2.  Writes this block's partial of ||r_{i+1}||^2, or carries the
-// block's rr_i partial forward when the block is idle (so an idle solve stays idle).
-struct CtlUpdate {
+// block's rr_i partial forward when the block is idle (so an idle solve stays idle).  XM is the
+// x-update form of the matching EpiUpdate: a skipping step records alpha and whether it worked,
+// a paired step reads them (two kernels later, so no block reads what another writes).
+template <int XM = kXPlain>
+struct CtlUpdateT {
     static constexpr bool kEnd = true;
     const double* rr_i;
     const double* rr_im1;
@@ -779,11 +824,18 @@ struct CtlUpdate {
     double* rr_next;
     CgScalars* sc;
     int slots;
-    using Pre = PartialsPre<3>;
+    struct Pre : PartialsPre<3> {
+        double alpha_prev;
+        int x_pending;
+    };
     __device__ Pre prefetch(int rhs) const {
         const long long o = (long long)rhs * slots;
         const double* const p[3] = {rr_i + o, rr_im1 + o, tt + o};
-        return prefetch_partials<3>(p, slots, sc[rhs]);
+        Pre pre;
+        static_cast<PartialsPre<3>&>(pre) = prefetch_partials<3>(p, slots, sc[rhs]);
+        pre.alpha_prev = XM == kXPair ? sc[rhs].alpha_prev : 0.0;
+        pre.x_pending = XM == kXPair ? sc[rhs].x_pending : 0;
+        return pre;
     }
     __device__ Scal begin(int rhs, int slot, double* lds) const { return begin(rhs, slot, lds, prefetch(rhs)); }
     __device__ Scal begin(int rhs, int slot, double* lds, const Pre& pre) const {
@@ -802,15 +854,20 @@ struct CtlUpdate {
             sc[rhs].iters = pre.iters + 1;
             sc[rhs].rr_last = a;
         }
-        return {open, alpha, beta};
+        if (XM == kXSkip && slot == 0 && threadIdx.x == 0) {
+            sc[rhs].x_pending = open;
+            if (open) sc[rhs].alpha_prev = alpha;
+        }
+        return {open, alpha, beta, pre.alpha_prev, pre.x_pending};
     }
     __device__ void end(double acc, int rhs, int slot, const Scal& s, double* lds) const {
         const double v = block_sum(acc, lds);
         const long long k = (long long)rhs * slots + slot;
         if (threadIdx.x == 0) rr_next[k] = s.open ? v : rr_i[k];
     }
-    CtlUpdate with_slots(int) const { return *this; }
+    CtlUpdateT with_slots(int) const { return *this; }
 };
+using CtlUpdate = CtlUpdateT<kXPlain>;
 
 // ----------------------------------------------------------------------------- fused kernel
 // One workgroup per (right-hand side, destination slice): the source slice lives in
@@ -1287,6 +1344,19 @@ k_exp_poly(const OpTab<R> T, const PolyCoef<R> pc, const Src src, const Epi epi,
                     epi.store(rhs, t, grow(r0 + r) * L + n2, scale(pc.scale, ya[r]), ea[r], T, sc, acc);
                     epi.store(rhs, t, LL + grow(r0 + r) * L + n2, scale(pc.scale, yb[r]), eb[r], T, sc, acc);
                 }
+        }
+    } else if (sc.pending) {
+        // an idle block of a paired x update whose previous step skipped x: add the pending term
+        if constexpr (EpiHasClosed<Epi>::value) {
+            if constexpr (!kEpiEarly) fetch_epi();
+            if (out_lane) {
+#pragma unroll
+                for (int r = 0; r < RM; ++r)
+                    if (out_row(r)) {
+                        epi.closed(rhs, t, grow(r0 + r) * L + n2, ea[r], T, sc);
+                        epi.closed(rhs, t, LL + grow(r0 + r) * L + n2, eb[r], T, sc);
+                    }
+            }
         }
     }
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);

@@ -289,3 +289,49 @@ def test_cg_continues_the_recursion_after_an_idle_stretch(prec, seed):
         assert np.linalg.norm(r[k]) <= 2e-10 * np.linalg.norm(chi[k]), k
     # the fixed recursion needs 27-60 iterations here; the stale direction took 150 to 3000+
     assert max(res.iters) <= 100, res.iters
+
+
+@pytest.mark.parametrize("every", [7, 50, 1])
+def test_cg_paired_x_updates_at_the_precision_workload(every):
+    """L = 51, N_t = 128 in mixed precision: the FP32 iterations on the polynomial stencil add
+    alpha p to x every other iteration (two terms at a time), with blocks of odd length (every =
+    7: the block's last iteration adds its own term), even length and one iteration.  A lost
+    term would leave the reliable update's true residual above the iterated one and cost extra
+    blocks; the solve instead meets tol on the oracle's residual (Sec. 2 eq. "hamiltonian") in
+    about the FP64 solve's iterations and with no more reliable updates than its iterations need."""
+    from workloads import draw_weak_field
+    w = PREC
+    print(f"[case] cg paired x updates {w.name} every={every}", flush=True)
+    phi, chi = draw_weak_field(w, seed=5)
+    op = oracle_op(w, mode="expm")
+    hub = _hub(w)
+    P, C = to_dev(phi), to_dev(chi)
+    res = hub.cg_solve(P, C, tol=1e-10, prec="mixed", reliable_every=every)
+    ref = hub.cg_solve(P, C, tol=1e-10, prec="fp64", reliable_every=every)
+    assert res.converged and ref.converged, (res.true_rel_res, ref.true_rel_res)
+    x = to_np(res.x)
+    rel = np.linalg.norm(chi - op.apply_A(phi, x)) / np.linalg.norm(chi)
+    assert rel <= 1.05e-10, rel
+    assert res.iters[0] <= 1.03 * ref.iters[0] + 10, (res.iters, ref.iters)
+    assert res.reliable_updates[0] <= -(-res.iters[0] // every) + 1, (res.reliable_updates, res.iters)
+
+
+@pytest.mark.parametrize("max_iter", [125, 126])
+def test_cg_paired_x_updates_at_a_max_iter_cut(max_iter):
+    """A mixed solve cut by max_iter inside a block (blocks of 50: the last one has 25 or 26
+    iterations, so it ends on a term of its own or on a pair): at the final reliable update the
+    FP64 residual of the folded x equals the FP32 recursion's to well within its size, which a
+    term missing from x would break; the returned x has the residual the solver reports."""
+    from workloads import draw_weak_field
+    w = PREC
+    print(f"[case] cg paired x updates, cut at {max_iter}", flush=True)
+    phi, chi = draw_weak_field(w, seed=6)
+    op = oracle_op(w, mode="expm")
+    hub = _hub(w)
+    res = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-10, prec="mixed", max_iter=max_iter,
+                       raise_on_error=False)
+    assert not res.converged and res.iters[0] == max_iter, (res.status, res.iters)
+    tr, rec = res.true_rel_res[0], res.recursive_rel_res[0]
+    assert abs(tr - rec) <= 1e-2 * tr, (tr, rec)
+    rel = np.linalg.norm(chi - op.apply_A(phi, to_np(res.x))) / np.linalg.norm(chi)
+    assert abs(rel - tr) <= 1e-6 * tr, (rel, tr)
