@@ -253,17 +253,10 @@ hub_status run_poly(hub_ctx* c, int nrhs, const OpTab<R>& T, const Src& src, con
     return launch_poly<R, 102>(c, nrhs, T, pc, src, epi, ctl, st);
 }
 
-// Apply E between a source functor and an epilogue functor over nrhs right-hand sides.
+// The kernels of one OpKind between a source functor and an epilogue functor.
 template <typename R, class Src, class Epi, class Ctl>
-hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ctl& ctl_in, hipStream_t st) {
-    const OpTab<R> T = op_tab<R>(c);
-    const OpKind kind = op_kind<R>(c, nrhs);
-    const Ctl ctl = ctl_in.with_slots(op_slots<R>(c, nrhs));
-    // the paired x update (EpiUpdate kXSkip / kXPair) is built for the polynomial stencil only
-    if constexpr (EpiXMode<Epi>::value != kXPlain) {
-        if (kind != OpKind::Poly) return fail(HUB_ERR_ARG, "internal: paired x updates need the polynomial stencil");
-        return run_poly<R>(c, nrhs, T, src, epi, ctl, st);
-    } else {
+hub_status run_kind(hub_ctx* c, int nrhs, OpKind kind, const OpTab<R>& T, const Src& src, const Epi& epi,
+                    const Ctl& ctl, hipStream_t st) {
     const size_t lds = fused_lds<R>(c);
     switch (kind) {
         case OpKind::Sub102: {
@@ -327,6 +320,20 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
     hipLaunchKernelGGL(k3, dim3(nrow_blocks), dim3(kThreads), lds_rows, st, T, G, static_cast<const cx<R>*>(W),
                        epi, ctl);
     return launch_check("k_split_rows_inv");
+}
+
+// Apply E between a source functor and an epilogue functor over nrhs right-hand sides.
+template <typename R, class Src, class Epi, class Ctl>
+hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ctl& ctl_in, hipStream_t st) {
+    const OpTab<R> T = op_tab<R>(c);
+    const OpKind kind = op_kind<R>(c, nrhs);
+    const Ctl ctl = ctl_in.with_slots(op_slots<R>(c, nrhs));
+    // the paired x update (EpiUpdate kXSkip / kXPair) is built for the polynomial stencil only
+    if constexpr (EpiXMode<Epi>::value != kXPlain) {
+        if (kind != OpKind::Poly) return fail(HUB_ERR_ARG, "internal: paired x updates need the polynomial stencil");
+        return run_poly<R>(c, nrhs, T, src, epi, ctl, st);
+    } else {
+        return run_kind<R>(c, nrhs, kind, T, src, epi, ctl, st);
     }
 }
 
@@ -558,8 +565,8 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     // copy of the angles instead, half the bytes of a table, and evaluate the phase per use on
     // the hardware sin/cos units.
     const bool angles = lin || (sizeof(Rlo) == sizeof(float) && op_kind<Rlo>(c, nrhs) == OpKind::Poly);
-    // the FP32 iterations on the polynomial stencil update x every other iteration (EpiUpdate)
-    const bool paired = !lin && sizeof(Rlo) == sizeof(float) && op_kind<Rlo>(c, nrhs) == OpKind::Poly;
+    // iterations on the polynomial stencil update x every other iteration (EpiUpdate)
+    const bool paired = !lin && op_kind<Rlo>(c, nrhs) == OpKind::Poly;
     cx<double>* ph64 = static_cast<cx<double>*>(c->ph64);
     const cx<Rlo>* ph_lo = reinterpret_cast<const cx<Rlo>*>(ph64);
     const Rlo* phi_lo = reinterpret_cast<const Rlo*>(phi);
@@ -656,27 +663,29 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
             const CtlSearch k1{pr(i), pr(i + 2), pt, sc, slots};
             const CtlUpdate k2{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
             hub_status q;
-            if constexpr (sizeof(Rlo) == sizeof(float)) if (paired) {
+            if (paired) {
                 // iteration j of its block (blocks of reliable_every iterations, the last cut by
                 // max_iter): even j skips x, odd j adds both terms; an even j that ends its
-                // block updates x plainly, so no term is pending at the reliable update
+                // block updates x plainly, so no term is pending at the reliable update.  The
+                // phases as the unpaired iterations take them: FP32 angles, or the FP64 table.
                 const long long b0 = i - i % o.reliable_every, j = i - b0;
                 const long long len = std::min<long long>(o.reliable_every, o.max_iter - b0);
                 const int xm = (j % 2 == 1) ? kXPair : (j + 1 < len ? kXSkip : kXPlain);
-                q = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p},
-                                EpiSearchMdag<Rlo, PhAngle<Rlo>>{rlo, p, tv, ang_lo}, k1, st);
+                const auto ph = [&] {
+                    if constexpr (sizeof(Rlo) == sizeof(float)) return ang_lo;
+                    else return tab_lo;
+                }();
+                using Ph = std::decay_t<decltype(ph)>;
+                q = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p}, EpiSearchMdag<Rlo, Ph>{rlo, p, tv, ph}, k1, st);
                 if (q != HUB_OK) return q;
                 if (xm == kXSkip)
-                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhAngle<Rlo>>{tv, ang_lo},
-                                    EpiUpdate<Rlo, kXSkip>{tv, p, xlo, rlo},
+                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, Ph>{tv, ph}, EpiUpdate<Rlo, kXSkip>{tv, p, xlo, rlo},
                                     CtlUpdateT<kXSkip>{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots}, st);
                 else if (xm == kXPair)
-                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhAngle<Rlo>>{tv, ang_lo},
-                                    EpiUpdate<Rlo, kXPair>{tv, p, xlo, rlo},
+                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, Ph>{tv, ph}, EpiUpdate<Rlo, kXPair>{tv, p, xlo, rlo},
                                     CtlUpdateT<kXPair>{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots}, st);
                 else
-                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, PhAngle<Rlo>>{tv, ang_lo},
-                                    EpiUpdate<Rlo>{tv, p, xlo, rlo}, k2, st);
+                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, Ph>{tv, ph}, EpiUpdate<Rlo>{tv, p, xlo, rlo}, k2, st);
                 if (q != HUB_OK) return q;
                 continue;
             }
