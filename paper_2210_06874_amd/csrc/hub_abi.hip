@@ -253,6 +253,24 @@ hub_status run_poly(hub_ctx* c, int nrhs, const OpTab<R>& T, const Src& src, con
     return launch_poly<R, 102>(c, nrhs, T, pc, src, epi, ctl, st);
 }
 
+// The compile-time L = 51 transform kernels: two workgroups per slice below kHalfBelow slices
+// (OpKind::Half51), else one (OpKind::Whole51).
+template <typename R, class Src, class Epi, class Ctl>
+hub_status run_fused51(hub_ctx* c, int nrhs, OpKind kind, const OpTab<R>& T, const Src& src, const Epi& epi,
+                       const Ctl& ctl, hipStream_t st) {
+    const size_t lds = fused_lds<R>(c);
+    if (kind == OpKind::Half51) {
+        auto kern = k_fused_ct<R, 51, kThreads51, true, Src, Epi, Ctl>;
+        allow_lds(kern, lds);
+        hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
+        return launch_check("k_fused_ct<51, half>");
+    }
+    auto kern = k_fused_ct<R, 51, kThreads51, false, Src, Epi, Ctl>;
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
+    return launch_check("k_fused_ct<51>");
+}
+
 // The kernels of one OpKind between a source functor and an epilogue functor.
 template <typename R, class Src, class Epi, class Ctl>
 hub_status run_kind(hub_ctx* c, int nrhs, OpKind kind, const OpTab<R>& T, const Src& src, const Epi& epi,
@@ -269,20 +287,11 @@ hub_status run_kind(hub_ctx* c, int nrhs, OpKind kind, const OpTab<R>& T, const 
             }
             return fail(HUB_ERR_ARG, "internal: sublattice kernel is FP32 only");
         }
-        case OpKind::Half51: {
-            auto kern = k_fused_ct<R, 51, kThreads51, true, Src, Epi, Ctl>;
-            allow_lds(kern, lds);
-            hipLaunchKernelGGL(kern, dim3(2 * nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
-            return launch_check("k_fused_ct<51, half>");
-        }
+        case OpKind::Half51:
+        case OpKind::Whole51:
+            return run_fused51<R>(c, nrhs, kind, T, src, epi, ctl, st);
         case OpKind::Poly:
             return run_poly<R>(c, nrhs, T, src, epi, ctl, st);
-        case OpKind::Whole51: {
-            auto kern = k_fused_ct<R, 51, kThreads51, false, Src, Epi, Ctl>;
-            allow_lds(kern, lds);
-            hipLaunchKernelGGL(kern, dim3(nrhs * c->Nt), dim3(kThreads51), lds, st, T, src, epi, ctl);
-            return launch_check("k_fused_ct<51>");
-        }
         case OpKind::Generic: {
             auto kern = k_fused<R, Src, Epi, Ctl>;
             allow_lds(kern, lds);
@@ -328,10 +337,15 @@ hub_status run_op(hub_ctx* c, int nrhs, const Src& src, const Epi& epi, const Ct
     const OpTab<R> T = op_tab<R>(c);
     const OpKind kind = op_kind<R>(c, nrhs);
     const Ctl ctl = ctl_in.with_slots(op_slots<R>(c, nrhs));
-    // the paired x update (EpiUpdate kXSkip / kXPair) is built for the polynomial stencil only
+    // the paired x update (EpiUpdate kXSkip / kXPair) is built into the polynomial stencil and,
+    // for FP64, the L = 51 transform kernels only (cg_impl pairs nothing else)
     if constexpr (EpiXMode<Epi>::value != kXPlain) {
-        if (kind != OpKind::Poly) return fail(HUB_ERR_ARG, "internal: paired x updates need the polynomial stencil");
-        return run_poly<R>(c, nrhs, T, src, epi, ctl, st);
+        if (kind == OpKind::Poly) return run_poly<R>(c, nrhs, T, src, epi, ctl, st);
+        if constexpr (sizeof(R) == sizeof(double)) {
+            if (kind == OpKind::Half51 || kind == OpKind::Whole51)
+                return run_fused51<R>(c, nrhs, kind, T, src, epi, ctl, st);
+        }
+        return fail(HUB_ERR_ARG, "internal: no paired x update for this kernel");
     } else {
         return run_kind<R>(c, nrhs, kind, T, src, epi, ctl, st);
     }
@@ -565,8 +579,12 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     // copy of the angles instead, half the bytes of a table, and evaluate the phase per use on
     // the hardware sin/cos units.
     const bool angles = lin || (sizeof(Rlo) == sizeof(float) && op_kind<Rlo>(c, nrhs) == OpKind::Poly);
-    // iterations on the polynomial stencil update x every other iteration (EpiUpdate)
-    const bool paired = !lin && op_kind<Rlo>(c, nrhs) == OpKind::Poly;
+    // iterations on the polynomial stencil, and FP64 ones on the L = 51 transform kernels, update
+    // x every other iteration (EpiUpdate)
+    const OpKind it_kind = op_kind<Rlo>(c, nrhs);
+    const bool paired = !lin && (it_kind == OpKind::Poly ||
+                                 (sizeof(Rlo) == sizeof(double) &&
+                                  (it_kind == OpKind::Half51 || it_kind == OpKind::Whole51)));
     cx<double>* ph64 = static_cast<cx<double>*>(c->ph64);
     const cx<Rlo>* ph_lo = reinterpret_cast<const cx<Rlo>*>(ph64);
     const Rlo* phi_lo = reinterpret_cast<const Rlo*>(phi);

@@ -1147,6 +1147,23 @@ k_fused_ct(const OpTab<R> T, const Src src, const Epi epi, const Ctl ctl) {
                 }
             }
         }
+    } else if (sc.pending) {
+        // an idle block of a paired x update whose previous step skipped x: add the pending term
+        // at the sites this block writes
+        if constexpr (EpiHasClosed<Epi>::value) {
+#pragma unroll
+            for (int rd = 0; rd < ROUNDSO; ++rd) {
+                const int task = tid + rd * NT;
+                if (task < NTE) {
+                    const int line = task / M0, np = task - line * M0;
+#pragma unroll
+                    for (int i = 0; i < R0; ++i) {
+                        const int k = off + line * L + np + i * M0;
+                        epi.closed(rhs, t, k, epi.fetch(rhs, t, k, T), T, sc);
+                    }
+                }
+            }
+        }
     }
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);
 }
