@@ -579,12 +579,11 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
     // copy of the angles instead, half the bytes of a table, and evaluate the phase per use on
     // the hardware sin/cos units.
     const bool angles = lin || (sizeof(Rlo) == sizeof(float) && op_kind<Rlo>(c, nrhs) == OpKind::Poly);
-    // iterations on the polynomial stencil, and FP64 ones on the L = 51 transform kernels, update
-    // x every other iteration (EpiUpdate)
+    // iterations on the stencils (the polynomial one, the linear form's) and FP64 ones on the
+    // L = 51 transform kernels update x every other iteration (EpiUpdate, LOutUpdate)
     const OpKind it_kind = op_kind<Rlo>(c, nrhs);
-    const bool paired = !lin && (it_kind == OpKind::Poly ||
-                                 (sizeof(Rlo) == sizeof(double) &&
-                                  (it_kind == OpKind::Half51 || it_kind == OpKind::Whole51)));
+    const bool paired = lin || it_kind == OpKind::Poly ||
+                        (sizeof(Rlo) == sizeof(double) && (it_kind == OpKind::Half51 || it_kind == OpKind::Whole51));
     cx<double>* ph64 = static_cast<cx<double>*>(c->ph64);
     const cx<Rlo>* ph_lo = reinterpret_cast<const cx<Rlo>*>(ph64);
     const Rlo* phi_lo = reinterpret_cast<const Rlo*>(phi);
@@ -677,46 +676,48 @@ hub_status cg_impl(hub_ctx* c, const double* phi, const cx<double>* chi, cx<doub
                 if (q != HUB_OK || done) return q;
             }
         }
+        // the phases as the iterations take them: FP32 angles (stencils), else the FP64 table
+        const auto ph = [&] {
+            if constexpr (sizeof(Rlo) == sizeof(float)) return ang_lo;
+            else return tab_lo;
+        }();
+        using Ph = std::decay_t<decltype(ph)>;
         for (long long i = from; i < from + n; ++i) {
             const CtlSearch k1{pr(i), pr(i + 2), pt, sc, slots};
             const CtlUpdate k2{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
-            hub_status q;
+            const CtlUpdateT<kXSkip> k2s{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
+            const CtlUpdateT<kXPair> k2p{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots};
+            // paired x updates: iteration j of its block (blocks of reliable_every iterations, the
+            // last cut by max_iter) skips x when j is even and adds both terms when j is odd; an
+            // even j that ends its block updates x plainly, so no term is pending at the reliable
+            // update
+            int xm = kXPlain;
             if (paired) {
-                // iteration j of its block (blocks of reliable_every iterations, the last cut by
-                // max_iter): even j skips x, odd j adds both terms; an even j that ends its
-                // block updates x plainly, so no term is pending at the reliable update.  The
-                // phases as the unpaired iterations take them: FP32 angles, or the FP64 table.
                 const long long b0 = i - i % o.reliable_every, j = i - b0;
                 const long long len = std::min<long long>(o.reliable_every, o.max_iter - b0);
-                const int xm = (j % 2 == 1) ? kXPair : (j + 1 < len ? kXSkip : kXPlain);
-                const auto ph = [&] {
-                    if constexpr (sizeof(Rlo) == sizeof(float)) return ang_lo;
-                    else return tab_lo;
-                }();
-                using Ph = std::decay_t<decltype(ph)>;
+                xm = (j % 2 == 1) ? kXPair : (j + 1 < len ? kXSkip : kXPlain);
+            }
+            hub_status q;
+            if (lin) {
+                q = run_lin<Rlo, true>(c, nrhs, ph, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
+                if (q != HUB_OK) return q;
+                if (xm == kXSkip)
+                    q = run_lin<Rlo, false>(c, nrhs, ph, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo, kXSkip>{p, xlo, rlo}, k2s, st);
+                else if (xm == kXPair)
+                    q = run_lin<Rlo, false>(c, nrhs, ph, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo, kXPair>{p, xlo, rlo}, k2p, st);
+                else
+                    q = run_lin<Rlo, false>(c, nrhs, ph, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
+            } else if (paired) {
                 q = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p}, EpiSearchMdag<Rlo, Ph>{rlo, p, tv, ph}, k1, st);
                 if (q != HUB_OK) return q;
                 if (xm == kXSkip)
-                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, Ph>{tv, ph}, EpiUpdate<Rlo, kXSkip>{tv, p, xlo, rlo},
-                                    CtlUpdateT<kXSkip>{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots}, st);
+                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, Ph>{tv, ph}, EpiUpdate<Rlo, kXSkip>{tv, p, xlo, rlo}, k2s,
+                                    st);
                 else if (xm == kXPair)
-                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, Ph>{tv, ph}, EpiUpdate<Rlo, kXPair>{tv, p, xlo, rlo},
-                                    CtlUpdateT<kXPair>{pr(i), pr(i + 2), pt, pr(i + 1), sc, slots}, st);
+                    q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, Ph>{tv, ph}, EpiUpdate<Rlo, kXPair>{tv, p, xlo, rlo}, k2p,
+                                    st);
                 else
                     q = run_op<Rlo>(c, nrhs, SrcPhasePrev<Rlo, Ph>{tv, ph}, EpiUpdate<Rlo>{tv, p, xlo, rlo}, k2, st);
-                if (q != HUB_OK) return q;
-                continue;
-            }
-            if (lin) {
-                if constexpr (sizeof(Rlo) == sizeof(float)) {
-                    q = run_lin<Rlo, true>(c, nrhs, ang_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
-                    if (q != HUB_OK) return q;
-                    q = run_lin<Rlo, false>(c, nrhs, ang_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
-                } else {
-                    q = run_lin<Rlo, true>(c, nrhs, tab_lo, LSrcSearch<Rlo>{rlo, p}, LOutSearch<Rlo>{tv}, k1, st);
-                    if (q != HUB_OK) return q;
-                    q = run_lin<Rlo, false>(c, nrhs, tab_lo, LSrcVec<Rlo>{tv}, LOutUpdate<Rlo>{p, xlo, rlo}, k2, st);
-                }
             } else if (angles) {
                 q = run_op<Rlo>(c, nrhs, SrcSearchNext<Rlo>{rlo, p},
                                 EpiSearchMdag<Rlo, PhAngle<Rlo>>{rlo, p, tv, ang_lo}, k1, st);

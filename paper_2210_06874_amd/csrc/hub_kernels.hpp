@@ -1979,22 +1979,43 @@ template <typename R>
 struct LPreUpdate {
     cx<R> p, x, r;
 };
-
 template <typename R>
+struct LPreUpdateNoX {
+    cx<R> p, r;
+};
+
+template <typename R, int XM = kXPlain>
 struct LOutUpdate {              // CG: q = M tv; p = r + beta p; x += alpha p; r -= alpha q; acc |r|^2
-    using Pre = LPreUpdate<R>;
+    // XM: how x is updated (kXPlain, kXSkip, kXPair; see EpiUpdate)
+    using Pre = std::conditional_t<XM == kXSkip, LPreUpdateNoX<R>, LPreUpdate<R>>;
+    static constexpr int kXMode = XM;
     cx<R>* p;
     cx<R>* x;
     cx<R>* r;
-    __device__ Pre fetch(long long k) const { return {p[k], x[k], r[k]}; }
+    __device__ Pre fetch(long long k) const {
+        if constexpr (XM == kXSkip) return {p[k], r[k]};
+        else return {p[k], x[k], r[k]};
+    }
     __device__ void store(long long k, cx<R> q, const Pre& a, const Scal& sc, double& acc) const {
         const R b = (R)sc.beta, al = (R)sc.alpha;
         const cx<R> pn = {a.r.re + b * a.p.re, a.r.im + b * a.p.im};
         const cx<R> rn = {a.r.re - al * q.re, a.r.im - al * q.im};
         p[k] = pn;
-        x[k] = {a.x.re + al * pn.re, a.x.im + al * pn.im};
+        if constexpr (XM == kXPlain) {
+            x[k] = {a.x.re + al * pn.re, a.x.im + al * pn.im};
+        } else if constexpr (XM == kXPair) {
+            const R ap = (R)sc.alpha_prev;
+            x[k] = {fmar(al, pn.re, fmar(ap, a.p.re, a.x.re)), fmar(al, pn.im, fmar(ap, a.p.im, a.x.im))};
+        }
         r[k] = rn;
         acc += (double)rn.re * (double)rn.re + (double)rn.im * (double)rn.im;
+    }
+    // a paired step of a right-hand side that went idle after the skip: add the pending term
+    __device__ void closed(long long k, const Pre& a, const Scal& sc) const {
+        if constexpr (XM == kXPair) {
+            const R ap = (R)sc.alpha_prev;
+            x[k] = {fmar(ap, a.p.re, a.x.re), fmar(ap, a.p.im, a.x.im)};
+        }
     }
 };
 
@@ -2130,6 +2151,11 @@ k_lin(const LinTab<R> T, const Ph ph, const Src src, const Out out, const Ctl ct
                 if (i < i1)
                     out.store(vb + row + i, lin_value<R, DAG>(T, ph, src, i, sgnA, sgnB, pre[j], sc), op[j], sc, acc);
             }
+        }
+    } else if (sc.pending) {
+        // an idle block of a paired x update whose previous step skipped x: add the pending term
+        if constexpr (EpiHasClosed<Out>::value) {
+            for (int i = first; i < i1; i += kLinThreads) out.closed(vb + row + i, out.fetch(vb + row + i), sc);
         }
     }
     if constexpr (Ctl::kEnd) ctl.end(acc, rhs, slot, sc, red_lds);

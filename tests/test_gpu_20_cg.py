@@ -316,20 +316,25 @@ def test_cg_paired_x_updates_at_the_precision_workload(every):
     assert res.reliable_updates[0] <= -(-res.iters[0] // every) + 1, (res.reliable_updates, res.iters)
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("form,prec", [("exp", "mixed"), ("exp", "fp64"), ("linear", "mixed"), ("linear", "fp64")])
 @pytest.mark.parametrize("max_iter", [125, 126])
-def test_cg_paired_x_updates_at_a_max_iter_cut(max_iter, prec):
+def test_cg_paired_x_updates_at_a_max_iter_cut(max_iter, form, prec):
     """A solve cut by max_iter inside a block (blocks of 50: the last one has 25 or 26
     iterations, so it ends on a term of its own or on a pair), in mixed precision (the polynomial
-    stencil) and FP64 (the transform kernels): at the final reliable update the FP64 residual of
-    the folded x equals the recursion's to well within its size, which a term missing from x
-    would break; the returned x has the residual the solver reports."""
+    stencil) and FP64 (the transform kernels), and in the linear form: at the final reliable
+    update the FP64 residual of the folded x equals the recursion's to well within its size,
+    which a term missing from x would break; the returned x has the residual the solver reports
+    (the oracle's operator of the same form recomputes it)."""
+    from paper_2210_06874_amd import Hubbard
     from workloads import draw_weak_field
     w = PREC
-    print(f"[case] cg paired x updates {prec}, cut at {max_iter}", flush=True)
+    print(f"[case] cg paired x updates {form} {prec}, cut at {max_iter}", flush=True)
     phi, chi = draw_weak_field(w, seed=6)
-    op = oracle_op(w, mode="expm")
-    hub = _hub(w)
+    if form == "exp":
+        op, hub = oracle_op(w, mode="expm"), _hub(w)
+    else:
+        op = O.LinearHubbardOperator(w.L, w.Nt, w.beta, w.kappa)
+        hub = Hubbard(w.L, w.Nt, w.beta, w.kappa, form="linear")
     res = hub.cg_solve(to_dev(phi), to_dev(chi), tol=1e-10, prec=prec, max_iter=max_iter,
                        raise_on_error=False)
     assert not res.converged and res.iters[0] == max_iter, (res.status, res.iters)
