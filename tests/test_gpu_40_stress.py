@@ -1,5 +1,6 @@
 """Large-volume stress workload: L = 102 (20,808 sites, the paper's largest lattice),
-Nt = 192, beta = 12, four right-hand sides solved together (three-kernel split path)."""
+Nt = 192, beta = 12, four right-hand sides solved together (the polynomial stencils in both
+precisions; the context's transform layout, for the operators that use one, is the split path)."""
 import numpy as np
 import pytest
 import torch

@@ -73,8 +73,8 @@ def test_whole_lattice_slab_reproduces_the_full_calls():
 
 def test_shards_of_the_stress_workload_sampled():
     """L = 102, N_t = 192, four right-hand sides: shards of 48 slices (the first, whose M halo
-    wraps, and the last, whose M^dag and force halos wrap), FP64 (split path) and FP32
-    (one-sublattice-at-a-time kernel), on each shard's edge slices against the oracle."""
+    wraps, and the last, whose M^dag and force halos wrap), FP64 and FP32 (the degree-9 and
+    degree-5 polynomial stencils), on each shard's edge slices against the oracle."""
     from paper_2210_06874_amd import Hubbard
     w = STRESS
     print(f"[case] slabs {w.name}", flush=True)
