@@ -214,10 +214,9 @@ def test_cg_free_plane_wave_at_scale(w, prec, path):
 
 
 def test_cg_two_rhs_at_the_precision_workload():
-    """L = 51, N_t = 128 with two right-hand sides: the iteration kernels run one workgroup
-    per slice (one right-hand side runs two per slice, with twice the reduction slots).  Both
-    solves meet tol on the oracle's own FP64 residual, and agree with one-rhs solves to within
-    the conditioning."""
+    """L = 51, N_t = 128 with two right-hand sides in every launch (the FP64 reliable updates'
+    transform kernels then run one workgroup per slice instead of two).  Both solves meet tol on
+    the oracle's own FP64 residual, and agree with one-rhs solves to within the conditioning."""
     from workloads import draw_weak_field
     w = PREC
     print(f"[case] cg two rhs {w.name}", flush=True)
