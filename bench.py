@@ -465,7 +465,7 @@ def main() -> int:
     tay_flops = w.N * (5 * 8.0 + 6.0 + 2.0)
     roof = {"bound": "hbm", "achieved": alg32 / t_k32 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": alg32 / t_k32 / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "hub_apply_M_c64 (k_exp_poly<float, 51, 512, 5, 2>: degree-5 polynomial of delta kappa K "
+            "kernel": "hub_apply_M_c64 (k_exp_poly<float, 51, 512, 5, 2, 1>: degree-5 polynomial of delta kappa K "
                       "as a stencil, two workgroups per slice)",
             "avg_launch_us": t_k32 * 1e6, "avg_launch_us_python_loop": t_loop32 * 1e6,
             "alg_bytes_per_launch": alg32, "site_slices_per_s": w.N / t_k32,
