@@ -155,14 +155,13 @@ def _stress_slices(op, phi, v, slices, dagger):
     return out
 
 
-@pytest.mark.parametrize("kernel", ["default", "sublattice", "split"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+# the sublattice kernel is FP32 only
+@pytest.mark.parametrize("prec,kernel", [("fp64", "default"), ("fp64", "split"), ("fp32", "default"),
+                                         ("fp32", "sublattice"), ("fp32", "split")])
 def test_apply_stress_workload_sampled(prec, kernel):
     """L = 102, Nt = 192, 4 right-hand sides in one call: sampled slices, including both wrap
     slices, against the oracle (the default polynomial stencil, degree 9 in FP64 and 5 in FP32;
     the forced split path; the FP32 sublattice kernel)."""
-    if prec == "fp64" and kernel == "sublattice":
-        pytest.skip("the sublattice kernel is FP32 only")
     w = STRESS
     print(f"[case] apply {prec} {w.name} {kernel}", flush=True)
     phi, v = draw_inputs(w, seed=15)
