@@ -331,6 +331,72 @@ def copy_floor(w, dev) -> dict:
     return out
 
 
+def dft_pass(w, dev) -> dict:
+    """One row pass of the per-slice L-point DFT over every row of every slice of the precision
+    workload (2 N_t tiles of L x L complex64, HBM to HBM, one workgroup per tile) in two forms from
+    the probe library: the library's own FFT stages on the VALU, and the dense DFT as a real GEMM
+    on the FP32 matrix cores.  Each is checked against numpy's FFT, then timed in a HIP graph.
+    Decides whether the transform belongs on MFMA."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2210_06874_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        raise RuntimeError(f"{B.PROBE_LIB} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(B.PROBE_LIB)
+    for f in (lib.probe_dft_rows_fft51, lib.probe_dft_rows_mfma51):
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+        f.restype = ctypes.c_int
+    L, ntiles = w.L, 2 * w.Nt
+    if L != 51:
+        raise ValueError("the probe kernels are compiled for L = 51")
+    rng = np.random.default_rng(5)
+    x_h = (rng.standard_normal((ntiles, L, L)) + 1j * rng.standard_normal((ntiles, L, L))).astype(np.complex64)
+    x = torch.from_numpy(x_h).to(dev)
+    y = torch.empty_like(x)
+    m = np.arange(L)
+    roots = torch.from_numpy(np.exp(-2j * np.pi * m / L).astype(np.complex64)).to(dev)
+    th = 2 * np.pi * np.outer(m, m) / L
+    G = np.zeros((104, 112))
+    G[:L, :L], G[:L, L:2 * L] = np.cos(th), -np.sin(th)
+    G[L:2 * L, :L], G[L:2 * L, L:2 * L] = np.sin(th), np.cos(th)
+    g = torch.from_numpy(G.astype(np.float32)).to(dev)
+    ref = np.fft.fft(x_h.astype(np.complex128), axis=-1)
+    scale = np.abs(ref).max()
+
+    def call(f, table):
+        rc = f(x.data_ptr(), y.data_ptr(), table.data_ptr(), ntiles,
+               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"probe launch failed: HIP error {rc}")
+
+    # 51 = 3 * 17, decimation in frequency: position 17 k + j holds frequency k + 3 j
+    pos = np.arange(L)
+    freq_at = pos // 17 + 3 * (pos % 17)
+    moved = 2.0 * ntiles * L * L * 8                         # bytes read + written per pass
+    mfma_flops = ntiles * 4 * (104 // 4) * (112 // 16) * 2 * 16 * 16 * 4   # issued per pass
+    out = {"what": "one row pass of the 51-point DFT over 2 Nt tiles of 51 x 51 complex64, HBM to HBM, "
+                   "HIP graph of 50 launches, events on its stream",
+           "bytes_moved": moved}
+    for name, f, table, perm in (("fft_valu", lib.probe_dft_rows_fft51, roots, freq_at),
+                                 ("dft_mfma_fp32", lib.probe_dft_rows_mfma51, g, pos)):
+        y.zero_()
+        call(f, table)
+        torch.cuda.synchronize()
+        err = float(np.abs(y.cpu().numpy() - ref[:, :, perm]).max() / scale)
+        if not err < 1e-5:
+            raise RuntimeError(f"probe {name}: error {err:.2e} against numpy's FFT")
+        t = time_graph(lambda: call(f, table), per_graph=50, replays=10)
+        r = {"us": t * 1e6, "GBs": moved / t / 1e9, "max_err_rel": err}
+        if name == "dft_mfma_fp32":
+            r["mfma_tflops"] = mfma_flops / t / 1e12
+            r["mfma_frac_of_fp32_peak"] = mfma_flops / t / 1e12 / 157.3
+        out[name] = r
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +413,9 @@ def main() -> int:
     ap.add_argument("--copy-floor", action="store_true",
                     help="only time plain device-to-device copies (HIP graphs) moving the bytes of one "
                          "FP32 / FP64 operator application and larger sizes, one JSON line")
+    ap.add_argument("--probe-dft", action="store_true",
+                    help="only check and time one DFT row pass at L = 51, Nt = 128 by the FFT stages "
+                         "(VALU) and as an FP32 MFMA GEMM (probe library), one JSON line")
     ap.add_argument("--no-persistent", action="store_true",
                     help="with --stress: leave out the persistent (cooperative) CG launch")
     ap.add_argument("--stress", action="store_true",
@@ -407,6 +476,9 @@ def main() -> int:
         return 0
     if args.copy_floor:
         print(json.dumps(copy_floor(w, dev)))
+        return 0
+    if args.probe_dft:
+        print(json.dumps(dft_pass(w, dev)))
         return 0
     # the headline input: the stored HMC field, heat-bath chi = M rho (rho seeded)
     phi_h, field_meta = load_hmc_field()

@@ -13,6 +13,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhubhip.so")
 
 SOURCES = ["hub_abi.hip", "hub_tables.cpp"]
+# a measurement probe kept out of the C ABI (bench.py --probe-dft): its own library
+PROBE_SOURCES = ["probe_dft_pass.hip"]
+PROBE_LIB = os.path.join(HERE, "libhubprobe.so")
 HEADERS = ["hub_internal.hpp", "hub_tables.hpp", "hub_fft.hpp", "hub_kernels.hpp", "hub_math.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -35,12 +38,20 @@ def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
 
 
 def build(verbose: bool = False, extra_flags=(), out: str | None = None) -> str:
-    """Compile every source for gfx950 and link libhubhip.so (or `out`); returns its path."""
+    """Compile every source for gfx950 and link libhubhip.so (or `out`); returns its path.
+    The default build also links the probe library libhubprobe.so."""
     lib = LIB if out is None else out
     build_dir = BUILD if out is None else lib + ".objs"
     os.makedirs(build_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda f: _compile(f, build_dir, tuple(extra_flags)), SOURCES))
+    srcs = SOURCES + (PROBE_SOURCES if out is None else [])
+    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(lambda f: _compile(f, build_dir, tuple(extra_flags)), srcs))
+    if out is None:
+        _link(objs[len(SOURCES):], PROBE_LIB, verbose)
+    return _link(objs[:len(SOURCES)], lib, verbose)
+
+
+def _link(objs, lib: str, verbose: bool) -> str:
     tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -37,6 +37,21 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(L.SIGNATURES), "binding and header disagree"
 
 
+def test_probe_library_exports_its_two_passes():
+    """The measurement probe (one DFT row pass by the FFT stages and as an FP32 MFMA GEMM) is
+    a library of its own, outside the C ABI: it loads and exports exactly its two entry points,
+    and the ABI library exports neither."""
+    L, _ = _lib()
+    from paper_2210_06874_amd import build as B
+    if not os.path.exists(B.PROBE_LIB):
+        pytest.skip("libhubprobe.so not built (run __graft_entry__.build())")
+    ctypes.CDLL(B.PROBE_LIB)
+    nm = lambda f: set(re.findall(r"\bT (probe_\w+)", subprocess.run(
+        ["nm", "-D", "--defined-only", f], capture_output=True, text=True).stdout))
+    assert nm(B.PROBE_LIB) == {"probe_dft_rows_fft51", "probe_dft_rows_mfma51"}
+    assert nm(L.LIB_PATH) == set()
+
+
 def test_struct_layouts_match_the_binding(tmp_path):
     L, _ = _lib()
     exe = tmp_path / "layout"
