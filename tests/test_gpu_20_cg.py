@@ -179,6 +179,16 @@ def test_cg_error_paths():
     pp, cp = ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(C.data_ptr())
     assert hub.lib.hub_apply_M(hub._h, pp, cp, pp, 1, None) == HUB_ERR_ARG
     assert hub.lib.hub_force(hub._h, pp, cp, pp, 1, None) == HUB_ERR_ARG
+    # an empty batch, a negative count and one beyond nrhs_max are refused before any launch,
+    # and the output is left as it was
+    out_v, out_g = torch.full_like(C, 7.0), torch.full_like(P, 7.0)
+    op_, gp = ctypes.c_void_p(out_v.data_ptr()), ctypes.c_void_p(out_g.data_ptr())
+    for n in (0, -1, 2):
+        assert hub.lib.hub_apply_M(hub._h, pp, cp, op_, n, None) == HUB_ERR_ARG
+        assert hub.lib.hub_apply_Mdag(hub._h, pp, cp, op_, n, None) == HUB_ERR_ARG
+        assert hub.lib.hub_force(hub._h, pp, cp, gp, n, None) == HUB_ERR_ARG
+    torch.cuda.synchronize()
+    assert bool((out_v == 7.0).all()) and bool((out_g == 7.0).all())
 
 
 def _free_cond(w):
