@@ -349,6 +349,8 @@ def dft_pass(w, dev) -> dict:
     for f in (lib.probe_dft_rows_fft51, lib.probe_dft_rows_mfma51):
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
         f.restype = ctypes.c_int
+    lib.probe_mfma_peak.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.probe_mfma_peak.restype = ctypes.c_int
     L, ntiles = w.L, 2 * w.Nt
     if L != 51:
         raise ValueError("the probe kernels are compiled for L = 51")
@@ -394,6 +396,23 @@ def dft_pass(w, dev) -> dict:
             r["mfma_tflops"] = mfma_flops / t / 1e12
             r["mfma_frac_of_fp32_peak"] = mfma_flops / t / 1e12 / 157.3
         out[name] = r
+    # the matrix cores' own rate: 1024 workgroups of four waves, each wave 8 * iters independent
+    # 16 x 16 x 4 MFMAs on register operands
+    nb, iters = 1024, 2048
+    rate = {}
+    for name, fp64, dt, sheet in (("fp32", 0, torch.float32, 157.3), ("fp64", 1, torch.float64, 78.6)):
+        buf = torch.empty(nb * 256, dtype=dt, device=dev)
+
+        def run(buf=buf, fp64=fp64):
+            rc = lib.probe_mfma_peak(buf.data_ptr(), nb, iters, fp64,
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            if rc != 0:
+                raise RuntimeError(f"probe launch failed: HIP error {rc}")
+        t = time_launches(run, 10, warm=3)
+        tf = nb * 4 * iters * 8 * 2048 / t / 1e12
+        rate[name] = {"tflops": tf, "datasheet_tflops": sheet, "frac_of_datasheet": tf / sheet}
+    out["mfma_rate"] = rate
+    out["dft_mfma_fp32"]["mfma_frac_of_measured_rate"] = out["dft_mfma_fp32"]["mfma_tflops"] / rate["fp32"]["tflops"]
     return out
 
 

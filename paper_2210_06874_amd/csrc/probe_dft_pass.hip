@@ -9,7 +9,8 @@
 //     with G = [[C, -S], [S, C]], C and S the cosine and sine of 2 pi k n / L, K = 2L padded
 //     to 104 and N = 2L to 112, v_mfma_f32_16x16x4f32 tiles; output in natural order.
 // The question it answers is whether the transform belongs on MFMA (the per-slice DFT is a
-// dense L x L contraction): bench.py --probe-dft times both.
+// dense L x L contraction): bench.py --probe-dft times both, and the matrix cores' own FP32 and
+// FP64 rates beside them.
 #include <hip/hip_runtime.h>
 
 #include "hub_fft.hpp"
@@ -78,9 +79,49 @@ __global__ void __launch_bounds__(256) k_probe_mfma_rows(const float* __restrict
     for (int i = threadIdx.x; i < 2 * L * L; i += 256) y[base + i] = xs[i];
 }
 
+// The matrix cores' own rate: every wave issues `iters` rounds of eight independent 16 x 16 x 4
+// MFMAs (FP32 or FP64) on register operands, with nothing else in the loop; the sums are stored
+// so that the work stays live.
+template <typename T>
+__global__ void __launch_bounds__(256) k_probe_mfma_peak(T* __restrict__ out, int iters) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    v4 acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = v4{0, 0, 0, 0};
+    const T a = (T)(threadIdx.x & 63) * (T)1e-3, b = (T)(blockIdx.x & 63) * (T)1e-3;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if constexpr (sizeof(T) == sizeof(float))
+                acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[k], 0, 0, 0);
+            else
+                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
+        }
+    }
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+    out[(long long)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
 }  // namespace
 
 extern "C" {
+
+// The FP32 (fp64 = 0) or FP64 (fp64 = 1) MFMA rate: nblocks workgroups of four waves, each wave
+// issuing iters * 8 MFMAs of 16 x 16 x 4 (2048 flops each).  out: device, nblocks * 256 floats
+// (or doubles).  Returns 0, or the HIP error of the launch.
+int probe_mfma_peak(void* out, int nblocks, int iters, int fp64, void* stream) {
+    if (nblocks <= 0 || iters <= 0) return 0;
+    if (fp64)
+        hipLaunchKernelGGL(k_probe_mfma_peak<double>, dim3(nblocks), dim3(256), 0, (hipStream_t)stream,
+                           static_cast<double*>(out), iters);
+    else
+        hipLaunchKernelGGL(k_probe_mfma_peak<float>, dim3(nblocks), dim3(256), 0, (hipStream_t)stream,
+                           static_cast<float*>(out), iters);
+    return (int)hipGetLastError();
+}
+
 
 // Row pass of the 51-point DFT by the library's FFT stages.  x, y: device, ntiles * 51 * 51
 // complex64 each (distinct buffers); roots: device, 51 complex64, roots[m] = e^{-2 pi i m / 51};

@@ -37,10 +37,10 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(L.SIGNATURES), "binding and header disagree"
 
 
-def test_probe_library_exports_its_two_passes():
+def test_probe_library_exports_its_entry_points():
     """The measurement probe (one DFT row pass by the FFT stages and as an FP32 MFMA GEMM) is
-    a library of its own, outside the C ABI: it loads and exports exactly its two entry points,
-    and the ABI library exports neither."""
+    a library of its own, outside the C ABI, with the matrix cores' own rate beside them: it
+    loads and exports exactly its three entry points, and the ABI library exports none of them."""
     L, _ = _lib()
     from paper_2210_06874_amd import build as B
     if not os.path.exists(B.PROBE_LIB):
@@ -48,7 +48,7 @@ def test_probe_library_exports_its_two_passes():
     ctypes.CDLL(B.PROBE_LIB)
     nm = lambda f: set(re.findall(r"\bT (probe_\w+)", subprocess.run(
         ["nm", "-D", "--defined-only", f], capture_output=True, text=True).stdout))
-    assert nm(B.PROBE_LIB) == {"probe_dft_rows_fft51", "probe_dft_rows_mfma51"}
+    assert nm(B.PROBE_LIB) == {"probe_dft_rows_fft51", "probe_dft_rows_mfma51", "probe_mfma_peak"}
     assert nm(L.LIB_PATH) == set()
 
 

@@ -16,3 +16,6 @@ def test_dft_row_pass_probe_matches_numpy_fft():
         assert r[name]["max_err_rel"] < 1e-5, (name, r[name])
         assert r[name]["us"] > 0
     assert 0 < r["dft_mfma_fp32"]["mfma_frac_of_fp32_peak"] <= 1
+    # the matrix cores' own rate, measured beside the pass, is the datasheet's to within its clock
+    for prec in ("fp32", "fp64"):
+        assert 0.3 < r["mfma_rate"][prec]["frac_of_datasheet"] < 1.1, r["mfma_rate"]
