@@ -4,7 +4,7 @@ import pytest
 import torch
 
 import oracle as O
-from workloads import TINY, SMALL, DIFF_SUB, PREC, STRESS, Lattice, draw_inputs, draw_complex, draw_phi
+from workloads import TINY, SMALL, PREC, STRESS, Lattice, draw_inputs, draw_complex, draw_phi
 from gpu_common import dev, to_dev, to_np, oracle_op
 import closed_forms as CF
 

@@ -5,8 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-import oracle as O
-from workloads import STRESS, draw_weak_field, draw_complex, draw_inputs
+from workloads import STRESS, draw_weak_field, draw_complex
 from gpu_common import dev, to_dev, to_np, oracle_op, assert_close_elementwise
 
 pytestmark = pytest.mark.gpu

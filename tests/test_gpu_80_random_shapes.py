@@ -4,7 +4,6 @@ M in FP32, the force on random vectors and, for the smaller ones, a mixed-precis
 against the oracle."""
 import numpy as np
 import pytest
-import torch
 
 import oracle as O
 from workloads import Lattice, draw_phi, draw_complex

@@ -1,7 +1,6 @@
 """GPU test of hub_force_noalloc (the force entry point that allocates nothing): through the C ABI
 it must give hub_force's result, on two calls in a row (the second with fewer right-hand sides
 and then a smaller lattice), and refuse sizes beyond its static scratch."""
-import ctypes
 
 import numpy as np
 import pytest
