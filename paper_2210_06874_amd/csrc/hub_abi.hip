@@ -26,8 +26,9 @@ constexpr int kHalfBelow = 256;     // two workgroups per slice below this many 
 // the 51 columns, four the 102 (each range plus its halos fits 32 lanes); 512 threads: 16 strips
 // of 3-4 rows (L = 51; 768 and 1024 measured slower in CG) or 6-7 rows (L = 102).
 // FP64 operators at L = 102 by the degree-9 series (2.9e-17 at x = 0.1875; kPolyTol64 is a third
-// of FP64's unit roundoff), six workgroups per slice (17 columns and 5 halos a side fit 32 lanes):
-// there the transforms need the three-kernel split path.  At L = 51 the FP64 stencil (four
+// of FP64's unit roundoff), five workgroups per slice (20-21 columns and 5 halos a side fit 32
+// lanes; six, 17 columns each, measured 13 % slower): there the transforms need the three-kernel
+// split path.  At L = 51 the FP64 stencil (four
 // workgroups per slice) measured 21.4 us per application against 17.9 us for the in-LDS
 // transforms, so FP64 at L = 51 keeps those.
 constexpr double kPolyMaxX = 0.25;
@@ -39,7 +40,7 @@ constexpr int kThreadsPoly = 512;
 template <typename R>
 constexpr int poly_deg() { return sizeof(R) == sizeof(float) ? kPolyDeg : kPolyDeg64; }
 template <typename R>
-constexpr int poly_split(int L) { return sizeof(R) == sizeof(double) ? 6 : (L == 51 ? 2 : 4); }
+constexpr int poly_split(int L) { return sizeof(R) == sizeof(double) ? 5 : (L == 51 ? 2 : 4); }
 // row groups: FP64 holds 4 rows per lane in two groups of 51 rows and 5 halos a side (7 rows per
 // lane, all 102 rows in one group, spilled in the CG kernels)
 template <typename R>
